@@ -1,0 +1,440 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics.
+
+Each test checks the oracle against something other than itself: Fourier
+closed forms, exact rationals, gauge symmetry, Hermiticity, locality, a dense
+brute-force operator on a 2^4 lattice, the Clifford algebra, Fierz
+completeness and gamma_5 hermiticity.  Smearing operator reading:
+(1 + kappa H)^N with H the gauge-covariant spatial hopping term; its
+unit-gauge eigenvalues are 1 + 2 kappa sum_i cos p_i.
+"""
+
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_5596_amd import synth
+
+
+def unit_links(dims):
+    V = synth.volume(dims)
+    U = np.zeros((4, V, 3, 3), dtype=np.complex128)
+    U[:] = np.eye(3)
+    return U
+
+
+def fourier_smear(dims, psi, kappa, n):
+    """(1 + kappa H)^n for unit links via the eigenvalues of the spatial
+    hopping term: plane waves, lambda(p) = 1 + 2 kappa sum_i cos p_i."""
+    Lx, Ly, Lz, Lt = dims
+    a = psi.reshape(Lt, Lz, Ly, Lx, -1)
+    f = np.fft.fftn(a, axes=(1, 2, 3))
+    pz = 2 * np.pi * np.arange(Lz) / Lz
+    py = 2 * np.pi * np.arange(Ly) / Ly
+    px = 2 * np.pi * np.arange(Lx) / Lx
+    lam = 1 + 2 * kappa * (np.cos(pz)[:, None, None] + np.cos(py)[None, :, None]
+                           + np.cos(px)[None, None, :])
+    f = f * (lam ** n)[None, :, :, :, None]
+    return np.fft.ifftn(f, axes=(1, 2, 3)).reshape(psi.shape)
+
+
+def gauge_rotate_links(dims, U, g):
+    """U^g_mu(x) = g(x) U_mu(x) g(x + mu)^dagger."""
+    out = np.empty_like(U)
+    for mu in range(4):
+        g_fwd = oracle.shift(g, dims, mu, +1)
+        out[mu] = np.einsum("vab,vbc,vdc->vad", g, U[mu], np.conj(g_fwd))
+    return out
+
+
+def gauge_rotate_fermions(g, psi):
+    return np.einsum("vab,...vsb->...vsa", g, psi)
+
+
+# --------------------------------------------------------------------------
+# Geometry and shift (pins P6)
+# --------------------------------------------------------------------------
+
+def test_neighbour_wraps_periodically():
+    dims = (4, 6, 2, 8)
+    V = synth.volume(dims)
+    for s in [0, 3, 5, V - 1, 77]:
+        x = [s % 4, (s // 4) % 6, (s // 24) % 2, s // 48]
+        for mu in range(4):
+            for step in (+1, -1):
+                y = list(x)
+                y[mu] = (y[mu] + step) % dims[mu]
+                expect = y[0] + 4 * (y[1] + 6 * (y[2] + 2 * y[3]))
+                assert oracle.neighbour(dims, s, mu, step) == expect
+
+
+def test_shift_identities_bitwise():
+    dims = (4, 6, 2, 8)
+    rng = np.random.default_rng(0)
+    V = synth.volume(dims)
+    f = rng.normal(size=(V, 4, 3)) + 1j * rng.normal(size=(V, 4, 3))
+    for mu in range(4):
+        back = oracle.shift(oracle.shift(f, dims, mu, +1), dims, mu, -1)
+        assert np.array_equal(back, f)
+        g = f
+        for _ in range(dims[mu]):
+            g = oracle.shift(g, dims, mu, +1)
+        assert np.array_equal(g, f)
+
+
+def test_shift_matches_array_roll():
+    """shift(f, +mu)(x) = f(x + mu): compare with numpy's roll of the 4-D array."""
+    dims = (4, 6, 2, 8)
+    V = synth.volume(dims)
+    f = np.arange(V, dtype=np.float64).astype(np.complex128)
+    a = f.reshape(8, 2, 6, 4)
+    for mu, axis in zip(range(4), (3, 2, 1, 0)):
+        for sign in (+1, -1):
+            expect = np.roll(a, -sign, axis=axis).reshape(-1)
+            assert np.array_equal(oracle.shift(f, dims, mu, sign), expect)
+
+
+# --------------------------------------------------------------------------
+# Smearing: free field (P1, P2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims,n", [((4, 4, 4, 8), 10), ((2, 2, 2, 2), 10),
+                                    ((6, 4, 8, 2), 7), ((8, 8, 8, 2), 25)])
+def test_free_field_fourier_closed_form(dims, n):
+    kappa = 0.25
+    U = unit_links(dims)
+    src = synth.point_source(dims, [0, 7])
+    got = oracle.smear(U, src, dims, kappa, n)
+    for c in range(2):
+        expect = fourier_smear(dims, src[c].reshape(-1, 12), kappa, n).reshape(src[c].shape)
+        scale = np.abs(expect).max()
+        assert np.abs(got[c] - expect).max() <= 1e-13 * scale
+
+
+def test_free_field_random_source_fourier():
+    dims = (6, 4, 2, 3)
+    rng = np.random.default_rng(5)
+    V = synth.volume(dims)
+    psi = rng.normal(size=(1, V, 4, 3)) + 1j * rng.normal(size=(1, V, 4, 3))
+    got = oracle.smear(unit_links(dims), psi, dims, 0.13, 9)
+    expect = fourier_smear(dims, psi[0].reshape(V, 12), 0.13, 9).reshape(V, 4, 3)
+    assert np.abs(got[0] - expect).max() <= 1e-12 * np.abs(expect).max()
+
+
+def test_free_field_printed_values_4cubed():
+    """Unit links, point source, kappa = 1/4, N = 10 on 4^3 x 8: every value is
+    an integer over 4^10 and FP64 holds it exactly.  The sum over sites is
+    (1 + 6 kappa)^N (zero-momentum eigenvalue) and the sum of squares follows
+    from Parseval."""
+    dims = (4, 4, 4, 8)
+    out = oracle.smear(unit_links(dims), synth.point_source(dims, [0]), dims, 0.25, 10)[0]
+    phi = out[:, 0, 0]
+    assert phi.sum() == 2.5 ** 10  # 9536.7431640625 exactly
+    scaled = phi.real * 4 ** 10
+    assert np.array_equal(scaled, np.round(scaled))
+    assert np.all(phi.imag == 0)
+    # Parseval: sum |phi|^2 = Vs^-1 sum_p lambda(p)^(2N)
+    p = 2 * np.pi * np.arange(4) / 4
+    lam = 1 + 0.5 * (np.cos(p)[:, None, None] + np.cos(p)[None, :, None] + np.cos(p)[None, None, :])
+    parseval = np.sum(lam ** 20) / 64
+    assert abs(np.sum(np.abs(phi) ** 2) - parseval) <= 1e-12 * parseval
+    # the other 11 spin-colour components stay exactly zero
+    assert np.count_nonzero(out[:, 1:, :]) == 0 and np.count_nonzero(out[:, 0, 1:]) == 0
+
+
+def test_free_field_exact_walk_count():
+    """kappa = 1/4: 4^N psi_N(x) counts weighted lattice walks; computed here in
+    exact integer arithmetic by repeated neighbour addition on a 3x5x2 slice."""
+    dims = (3, 5, 2, 1)
+    n = 6
+    Lx, Ly, Lz, _ = dims
+    cnt = np.zeros((Lz, Ly, Lx), dtype=object)
+    cnt[0, 0, 0] = 1
+    for _ in range(n):
+        new = cnt * 4  # 4^k psi_k: the identity term carries the factor 4
+        for axis in range(3):
+            new = new + np.roll(cnt, 1, axis=axis) + np.roll(cnt, -1, axis=axis)
+        cnt = new
+    got = oracle.smear(unit_links(dims), synth.point_source(dims, [0]), dims, 0.25, n)[0]
+    expect = np.array([float(v) for v in cnt.reshape(-1)]) / 4 ** n
+    assert np.array_equal(got[:, 0, 0].real, expect)
+
+
+# --------------------------------------------------------------------------
+# Smearing: gauge covariance, Hermiticity, linearity, locality (P3, P8, P9)
+# --------------------------------------------------------------------------
+
+def test_gauge_covariance():
+    dims = (4, 4, 4, 8)
+    U = synth.su3_links(dims, 1)
+    psi = synth.gaussian_propagator(dims, 101, ncols=3)
+    g = synth.gauge_transform(dims, 9001)
+    lhs = oracle.smear(gauge_rotate_links(dims, U, g), gauge_rotate_fermions(g, psi), dims, 0.25, 10)
+    rhs = gauge_rotate_fermions(g, oracle.smear(U, psi, dims, 0.25, 10))
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
+
+
+def test_gauge_covariance_detects_wrong_link():
+    """Sanity of the pin itself: a hop that uses U_mu(x) on the backward
+    neighbour is not covariant, and the test above would catch it."""
+    dims = (4, 4, 2, 2)
+    U = synth.su3_links(dims, 2)
+    psi = synth.gaussian_propagator(dims, 102, ncols=1)[0]
+    g = synth.gauge_transform(dims, 9002)
+
+    def wrong_step(U, psi):
+        out = psi.copy()
+        for i in range(3):
+            out += 0.25 * np.einsum("vab,vsb->vsa", U[i], oracle.shift(psi, dims, i, +1))
+            out += 0.25 * np.einsum("vba,vsb->vsa", np.conj(U[i]), oracle.shift(psi, dims, i, -1))
+        return out
+
+    Ug = gauge_rotate_links(dims, U, g)
+    lhs = wrong_step(Ug, gauge_rotate_fermions(g, psi))
+    rhs = gauge_rotate_fermions(g, wrong_step(U, psi))
+    assert np.linalg.norm(lhs - rhs) > 1e-3 * np.linalg.norm(rhs)
+
+
+def test_hermiticity_and_linearity():
+    dims = (4, 2, 6, 3)
+    U = synth.su3_links(dims, 7)
+    a = synth.gaussian_propagator(dims, 11, ncols=1)[0]
+    b = synth.gaussian_propagator(dims, 12, ncols=1)[0]
+    Ma = oracle.smear_step(U, a, dims, 0.21)
+    Mb = oracle.smear_step(U, b, dims, 0.21)
+    lhs = np.vdot(b, Ma)
+    rhs = np.vdot(Mb, a)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    alpha, beta = 0.3 - 1.1j, 2.0 + 0.5j
+    comb = oracle.smear(U, alpha * a + beta * b, dims, 0.21, 4)[0]
+    sep = alpha * oracle.smear(U, a, dims, 0.21, 4)[0] + beta * oracle.smear(U, b, dims, 0.21, 4)[0]
+    assert np.linalg.norm(comb - sep) <= 1e-13 * np.linalg.norm(sep)
+
+
+def test_time_slice_locality():
+    dims = (4, 4, 4, 8)
+    U = synth.su3_links(dims, 1)
+    t0 = 3
+    src = synth.point_source(dims, range(12), site=t0 * 64 + 5)
+    out = oracle.smear(U, src, dims, 0.25, 10)
+    per_slice = np.abs(out).reshape(12, 8, 64, 12).sum(axis=(0, 2, 3))
+    assert per_slice[t0] > 0
+    assert np.count_nonzero(per_slice[np.arange(8) != t0]) == 0
+
+
+# --------------------------------------------------------------------------
+# Dense brute force on the 2^4 lattice (P7)
+# --------------------------------------------------------------------------
+
+def dense_operator(dims, U, kappa):
+    """192x192 matrix 1 + kappa H built by enumerating every (site, spatial
+    direction, sign) hop; hops that land on the same site add up."""
+    V = synth.volume(dims)
+    n = 12 * V
+    M = np.eye(n, dtype=np.complex128)
+
+    def coords(s):
+        return [s % dims[0], (s // dims[0]) % dims[1], (s // (dims[0] * dims[1])) % dims[2],
+                s // (dims[0] * dims[1] * dims[2])]
+
+    def index(c):
+        return c[0] + dims[0] * (c[1] + dims[1] * (c[2] + dims[2] * c[3]))
+
+    for s in range(V):
+        c = coords(s)
+        for i in range(3):
+            for sign in (+1, -1):
+                d = list(c)
+                d[i] = (d[i] + sign) % dims[i]
+                y = index(d)
+                link = U[i, s] if sign > 0 else np.conj(U[i, y]).T
+                for spin in range(4):
+                    rows = 12 * s + 3 * spin + np.arange(3)
+                    cols = 12 * y + 3 * spin + np.arange(3)
+                    M[np.ix_(rows, cols)] += kappa * link
+    return M
+
+
+def test_brute_force_2to4_smearing():
+    dims = (2, 2, 2, 2)
+    U = synth.su3_links(dims, 44)
+    M = dense_operator(dims, U, 0.25)
+    MN = np.linalg.matrix_power(M, 10)
+    src = synth.point_source(dims, range(12))
+    got = oracle.smear(U, src, dims, 0.25, 10)
+    for j in range(12):
+        expect = MN @ src[j].reshape(-1)
+        assert np.abs(got[j].reshape(-1) - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+def test_brute_force_2to4_contraction():
+    """Contraction via explicit 12x12 matrices and Kronecker products."""
+    dims = (2, 2, 2, 2)
+    S1 = synth.gaussian_propagator(dims, 45)
+    S2 = synth.gaussian_propagator(dims, 46)
+    got = oracle.meson(S1, S2, dims)
+    V = 16
+    g5 = np.kron(oracle.gamma(15), np.eye(3))
+    expect = np.zeros((16, 2), dtype=np.complex128)
+    for n in range(16):
+        G = np.kron(oracle.gamma(n), np.eye(3))
+        for s in range(V):
+            A = S1[:, s].reshape(12, 12).T  # rows sink (spin, colour), cols source j
+            B = S2[:, s].reshape(12, 12).T
+            expect[n, s // 8] += np.trace(g5 @ B.conj().T @ g5 @ G @ A @ G)
+    assert np.abs(got - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+# --------------------------------------------------------------------------
+# Gamma matrices (P11)
+# --------------------------------------------------------------------------
+
+def test_gamma_clifford_and_gamma5():
+    g = [oracle.gamma(1 << k) for k in range(4)]
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T, atol=0)
+        for b in range(4):
+            anti = g[a] @ g[b] + g[b] @ g[a]
+            assert np.array_equal(anti, 2 * np.eye(4) * (a == b))
+    assert np.array_equal(oracle.gamma(15), np.diag([1, 1, -1, -1]).astype(complex))
+    assert np.array_equal(oracle.gamma(0), np.eye(4, dtype=complex))
+    # gamma_4 in the DeGrand-Rossi basis couples upper and lower spin pairs
+    assert np.array_equal(np.abs(oracle.gamma(8)), np.kron([[0, 1], [1, 0]], np.eye(2)))
+
+
+def test_gamma_signed_permutations_klein_group():
+    klein = {(0, 1, 2, 3), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0)}
+    groups = {}
+    for n in range(16):
+        G = oracle.gamma(n)
+        perm = tuple(int(np.flatnonzero(G[r])[0]) for r in range(4))
+        assert all(np.count_nonzero(G[r]) == 1 for r in range(4))
+        assert perm in klein
+        assert all(abs(G[r, perm[r]]) == 1 for r in range(4))
+        groups.setdefault(perm, []).append(n)
+    assert sorted(map(tuple, groups.values())) == [(0, 3, 12, 15), (1, 2, 13, 14),
+                                                   (4, 7, 8, 11), (5, 6, 9, 10)]
+
+
+def test_gamma_squares():
+    for n in range(16):
+        k = bin(n).count("1")
+        eps = (-1) ** (k * (k - 1) // 2)
+        G = oracle.gamma(n)
+        assert np.array_equal(G @ G, eps * np.eye(4))
+
+
+# --------------------------------------------------------------------------
+# Contraction (P4, P10, Fierz completeness)
+# --------------------------------------------------------------------------
+
+def _epsilon(n):
+    k = bin(n).count("1")
+    return (-1) ** (k * (k - 1) // 2)
+
+
+def _spin_trace(S):
+    """(Tr_spin S)(x)_{ab} = sum_alpha S[(alpha a), (alpha b)], (V, 3, 3)."""
+    V = S.shape[1]
+    out = np.zeros((V, 3, 3), dtype=np.complex128)
+    for alpha in range(4):
+        for b in range(3):
+            out[:, :, b] += S[3 * alpha + b, :, alpha, :]
+    return out
+
+
+def test_contraction_gamma5_hermiticity_and_bounds():
+    dims = (4, 4, 2, 6)
+    S = synth.gaussian_propagator(dims, 33)
+    C = oracle.meson(S, S, dims)
+    per_site = np.sum(np.abs(S) ** 2, axis=(0, 2, 3)).reshape(6, -1).sum(axis=1)
+    assert np.abs(C[15] - per_site).max() <= 1e-13 * per_site.max()
+    assert np.abs(C.imag).max() <= 1e-13 * per_site.max()
+    assert np.all(np.abs(C) <= C[15].real[None, :] * (1 + 1e-13))
+    assert abs(C[15].sum() - np.sum(np.abs(S) ** 2)) <= 1e-13 * np.sum(np.abs(S) ** 2)
+
+
+def test_contraction_fierz_completeness():
+    """sum_n eps_n Gamma_n A Gamma_n = 4 Tr(A) 1  (eps_n = Gamma_n^2), so
+    sum_n eps_n C_n(t) = 4 sum_{x in t} Tr_c[(Tr_s S2)^dagger (Tr_s S1)]."""
+    dims = (2, 4, 2, 3)
+    S1 = synth.gaussian_propagator(dims, 51)
+    S2 = synth.gaussian_propagator(dims, 52)
+    C = oracle.meson(S1, S2, dims)
+    lhs = sum(_epsilon(n) * C[n] for n in range(16))
+    T1, T2 = _spin_trace(S1), _spin_trace(S2)
+    site = 4 * np.einsum("vab,vab->v", np.conj(T2), T1)
+    rhs = site.reshape(3, -1).sum(axis=1)
+    assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max()
+
+
+def test_contraction_gauge_invariance():
+    dims = (4, 4, 4, 4)
+    S1 = synth.gaussian_propagator(dims, 61)
+    S2 = synth.gaussian_propagator(dims, 62)
+    g = synth.gauge_transform(dims, 9003)
+    C = oracle.meson(S1, S2, dims)
+    Cg = oracle.meson(gauge_rotate_fermions(g, S1), gauge_rotate_fermions(g, S2), dims)
+    assert np.abs(C - Cg).max() <= 1e-13 * np.abs(C).max()
+
+
+def test_free_point_source_correlator_closed_form():
+    """Unit links, 12-column point source: S(x) = phi(x) 1_12 with phi the
+    free smeared scalar, so C_n(t0) = 12 eps_n sum_x phi(x)^2 and C_n(t) = 0
+    elsewhere; sum phi^2 comes from Parseval."""
+    dims = (4, 4, 4, 8)
+    S = oracle.smear(unit_links(dims), synth.point_source(dims, range(12)), dims, 0.25, 6)
+    C = oracle.meson(S, S, dims)
+    p = 2 * np.pi * np.arange(4) / 4
+    lam = 1 + 0.5 * (np.cos(p)[:, None, None] + np.cos(p)[None, :, None] + np.cos(p)[None, None, :])
+    sum_phi2 = np.sum(lam ** 12) / 64
+    for n in range(16):
+        assert abs(C[n, 0] - 12 * _epsilon(n) * sum_phi2) <= 1e-12 * sum_phi2
+        assert np.count_nonzero(C[n, 1:]) == 0
+
+
+def test_config1_pion_is_column_norm_per_slice():
+    """The one-column pion correlator C(t) = sum_x |psi(x, t)|^2 is the n = 15
+    term restricted to column 0 (the other columns zero)."""
+    dims = (4, 4, 4, 8)
+    U = synth.su3_links(dims, 1)
+    psi = oracle.smear(U, synth.point_source(dims, [0]), dims, 0.25, 10)
+    S = np.zeros((12,) + psi.shape[1:], dtype=np.complex128)
+    S[0] = psi[0]
+    C = oracle.meson(S, S, dims)
+    direct = np.sum(np.abs(psi[0]) ** 2, axis=(1, 2)).reshape(8, -1).sum(axis=1)
+    assert np.abs(C[15] - direct).max() <= 1e-13 * direct.max()
+    ts = oracle.timeslice_sum(np.sum(np.abs(psi[0]) ** 2, axis=(1, 2)), dims)[:, 0]
+    assert np.abs(ts - direct).max() <= 1e-13 * direct.max()
+
+
+# --------------------------------------------------------------------------
+# Sums
+# --------------------------------------------------------------------------
+
+def test_sums_against_integer_fields():
+    """Integer-valued fields make FP64 sums exact, independent of order."""
+    dims = (4, 2, 2, 5)
+    V = synth.volume(dims)
+    rng = np.random.default_rng(3)
+    f = rng.integers(-50, 50, size=(V, 3)) + 1j * rng.integers(-50, 50, size=(V, 3))
+    ts = oracle.timeslice_sum(f, dims)
+    assert np.array_equal(ts, f.reshape(5, -1, 3).sum(axis=1))
+    assert oracle.norm2(f) == float(np.sum(np.abs(f) ** 2))
+    g = rng.integers(-50, 50, size=(V, 3)) + 1j * rng.integers(-50, 50, size=(V, 3))
+    assert oracle.inner(f, g) == complex(np.sum(np.conj(f) * g))
+
+
+def test_golden_config1_regression():
+    """Stored oracle output (tests/golden/make_golden.py) still reproduces."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "config1_fp64.json")
+    gold = json.load(open(path))
+    dims = (4, 4, 4, 8)
+    psi = oracle.smear(synth.su3_links(dims, 1), synth.point_source(dims, [0]), dims, 0.25, 10)[0]
+    corr = oracle.timeslice_sum(np.sum(np.abs(psi) ** 2, axis=(1, 2)), dims)[:, 0].real
+    assert np.allclose(corr, gold["pion_correlator"], rtol=1e-13, atol=0)
+    # locality: only the source slice is populated
+    assert np.count_nonzero(corr[1:]) == 0
