@@ -1,0 +1,770 @@
+// Jacobi smearing on gfx950: the hot loop of source and sink smearing
+// (SRC / SNK, section 5 and Figure 4 of the paper).
+//
+//   psi_{k+1}(x) = psi_k(x) + kappa sum_{i=0,1,2} [ U_i(x) psi_k(x+i)
+//                                                + U_i(x-i)^dagger psi_k(x-i) ]
+//
+// One thread updates one site for a group of columns; the six links of the
+// site stay in registers and are reused by every column and spin, so the
+// 12-column update reads each link once from memory.  The 3x3 complex
+// mat-vecs run on the vector ALUs (there is no dense contraction to give to
+// the matrix cores).  F16S storage keeps links and spinors as half2 with a
+// per-record FP32 scale; products use v_dot2_f32_f16 (two half products
+// accumulated in FP32) and the per-term scales are applied in FP32.
+//
+// Every launch shape (sites per block, column groups, XCD mapping), the
+// single-lattice and the multi-lattice kernels, graph replay and eager
+// launches run the same per-site code, so they produce bitwise-identical
+// results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace qdpmi {
+
+struct SmearJob {
+    Geometry g;
+    const char* gauge;
+    const char* src[12];
+    char* dst[12];
+    int32_t ncols;
+    int32_t pad;
+};
+
+struct SmearLaunch {
+    int64_t site_begin;  // first checkerboard site of the pass
+    int64_t site_count;  // sites of the pass
+    int64_t nlogical;    // logical blocks (grid may be padded to 8)
+    int32_t site_waves;  // wavefronts of sites per block
+    int32_t col_groups;  // column groups per site
+    int32_t xcd;         // XCD-aware block mapping
+    int32_t pad;
+    double kappa;
+};
+
+// ---------------------------------------------------------------------------
+// Per-site update, FP64 / FP32 storage (arithmetic in the storage type)
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s, int c0, int c1,
+                                                 R kappa) {
+    using T2 = cplx_t<R>;
+    const int64_t plane = job.g.plane;
+    const SpatialNeighbours nb = spatial_neighbours(job.g, s);
+    const T2* __restrict__ U = reinterpret_cast<const T2*>(job.gauge);
+
+    T2 uf[3][9], ub[3][9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            uf[i][k] = U[(int64_t)(i * 9 + k) * plane + s];
+            ub[i][k] = U[(int64_t)(i * 9 + k) * plane + nb.bwd[i]];
+        }
+
+    for (int c = c0; c < c1; ++c) {
+        const T2* __restrict__ src = reinterpret_cast<const T2*>(job.src[c]);
+        T2 acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = T2{0, 0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            {
+                T2 v[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.fwd[i]];
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) cmac(acc[3 * sp + a], uf[i][3 * a + b], v[3 * sp + b]);
+            }
+            {
+                T2 v[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.bwd[i]];
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+                            cmac_conj(acc[3 * sp + a], ub[i][3 * b + a], v[3 * sp + b]);
+            }
+        }
+        T2* __restrict__ dst = reinterpret_cast<T2*>(job.dst[c]);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            T2 o = src[(int64_t)k * plane + s];
+            o.x = fmadd(kappa, acc[k].x, o.x);
+            o.y = fmadd(kappa, acc[k].y, o.y);
+            dst[(int64_t)k * plane + s] = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-site update, F16S storage (FP32 arithmetic)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float dot2(half2_t a, half2_t b, float c) {
+    return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+
+__device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s, int c0, int c1,
+                                                 float kappa) {
+    const int64_t plane = job.g.plane;
+    const SpatialNeighbours nb = spatial_neighbours(job.g, s);
+    const half2_t* __restrict__ U = reinterpret_cast<const half2_t*>(job.gauge);
+    const float* __restrict__ Us =
+        reinterpret_cast<const float*>(job.gauge + scale_offset(plane, 4, 9, 0));
+
+    // forward link u: re(u v) = (u.x, -u.y).v   im(u v) = (u.y, u.x).v
+    // backward link w: re(w* v) = (w.x, w.y).v  im(w* v) = (-w.y, w.x).v
+    half2_t fre[3][9], fim[3][9], bre[3][9], bim[3][9];
+    float sf[3], sb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        sf[i] = Us[(int64_t)i * plane + s];
+        sb[i] = Us[(int64_t)i * plane + nb.bwd[i]];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const half2_t u = U[(int64_t)(i * 9 + k) * plane + s];
+            const half2_t w = U[(int64_t)(i * 9 + k) * plane + nb.bwd[i]];
+            fre[i][k] = half2_t{u.x, (_Float16)(-u.y)};
+            fim[i][k] = half2_t{u.y, u.x};
+            bre[i][k] = w;
+            bim[i][k] = half2_t{(_Float16)(-w.y), w.x};
+        }
+    }
+
+    for (int c = c0; c < c1; ++c) {
+        const half2_t* __restrict__ src = reinterpret_cast<const half2_t*>(job.src[c]);
+        const float* __restrict__ ssc =
+            reinterpret_cast<const float*>(job.src[c] + scale_offset(plane, 1, 12, 0));
+        float2 acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            {
+                half2_t v[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.fwd[i]];
+                const float sc = sf[i] * ssc[nb.fwd[i]];
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        float tre = 0.f, tim = 0.f;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            tre = dot2(fre[i][3 * a + b], v[3 * sp + b], tre);
+                            tim = dot2(fim[i][3 * a + b], v[3 * sp + b], tim);
+                        }
+                        acc[3 * sp + a].x = fmadd(sc, tre, acc[3 * sp + a].x);
+                        acc[3 * sp + a].y = fmadd(sc, tim, acc[3 * sp + a].y);
+                    }
+            }
+            {
+                half2_t v[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.bwd[i]];
+                const float sc = sb[i] * ssc[nb.bwd[i]];
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        float tre = 0.f, tim = 0.f;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            tre = dot2(bre[i][3 * b + a], v[3 * sp + b], tre);
+                            tim = dot2(bim[i][3 * b + a], v[3 * sp + b], tim);
+                        }
+                        acc[3 * sp + a].x = fmadd(sc, tre, acc[3 * sp + a].x);
+                        acc[3 * sp + a].y = fmadd(sc, tim, acc[3 * sp + a].y);
+                    }
+            }
+        }
+        // psi + kappa * acc, then requantise the record
+        const float so = ssc[s];
+        float2 out[12];
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const float2 o = f16s_decode(src[(int64_t)k * plane + s], so);
+            out[k].x = fmadd(kappa, acc[k].x, o.x);
+            out[k].y = fmadd(kappa, acc[k].y, o.y);
+            m = fmaxf(m, fmaxf(fabsf(out[k].x), fabsf(out[k].y)));
+        }
+        const int e = f16s_exponent(m);
+        half2_t* __restrict__ dst = reinterpret_cast<half2_t*>(job.dst[c]);
+        float* __restrict__ dsc = reinterpret_cast<float*>(job.dst[c] + scale_offset(plane, 1, 12, 0));
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dst[(int64_t)k * plane + s] = f16s_encode(out[k].x, out[k].y, e);
+        dsc[s] = m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void site_update(const SmearJob& job, int32_t s, int c0, int c1,
+                                            double kappa) {
+    if constexpr (PREC == QDP_F64) {
+        site_update_real<double>(job, s, c0, c1, kappa);
+    } else if constexpr (PREC == QDP_F32) {
+        site_update_real<float>(job, s, c0, c1, (float)kappa);
+    } else {
+        site_update_f16s(job, s, c0, c1, (float)kappa);
+    }
+}
+
+// Thread -> (site, column group) inside a tile of 64 * site_waves sites.
+template <int PREC>
+__device__ __forceinline__ void tile_update(const SmearJob& job, int64_t tile, int64_t site_begin,
+                                           int64_t site_count, int site_waves, int col_groups,
+                                           double kappa) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int group = wave % col_groups, sw = wave / col_groups;
+    const int64_t local = (tile * site_waves + sw) * 64 + lane;
+    if (local >= site_count) return;
+    const int cpt = (job.ncols + col_groups - 1) / col_groups;
+    const int c0 = group * cpt;
+    const int c1 = min(job.ncols, c0 + cpt);
+    if (c0 >= c1) return;
+    site_update<PREC>(job, (int32_t)(site_begin + local), c0, c1, kappa);
+}
+
+// OCC is the occupancy target handed to the register allocator (waves per
+// SIMD; 0 = the compiler's choice).  More waves hide more memory latency but
+// leave fewer registers for the six links and the prefetched neighbours.
+template <int PREC, int OCC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_kernel(
+    SmearJob job, SmearLaunch ln) {
+    int64_t b = blockIdx.x;
+    if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
+    if (b >= ln.nlogical) return;
+    tile_update<PREC>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.kappa);
+}
+
+// Persistent multi-lattice kernel: a fixed grid walks a work list of
+// (lattice, tile) items; block b takes a contiguous run of items (XCD-aware
+// so one XCD's blocks share neighbouring tiles).
+template <int PREC, int OCC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_batch_kernel(
+    const SmearJob* __restrict__ jobs,
+                                                          const int64_t* __restrict__ tile_start,
+                                                          int32_t njobs, SmearLaunch ln) {
+    const int64_t ntiles = tile_start[njobs];
+    int64_t b = blockIdx.x;
+    if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = b * per;
+    const int64_t t1 = min(ntiles, t0 + per);
+    int j = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        while (j + 1 < njobs && tile_start[j + 1] <= t) ++j;  // tiles are ordered by job
+        if (t < tile_start[j]) {  // first tile of this run: binary search
+            int lo = 0, hi = njobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            j = lo;
+        }
+        const SmearJob& job = jobs[j];
+        tile_update<PREC>(job, t - tile_start[j], 0, job.g.V, ln.site_waves, ln.col_groups,
+                          ln.kappa);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Launch {
+    void* func;
+    dim3 grid, block;
+    std::vector<char> args;  // packed argument values
+    std::vector<size_t> arg_offsets;
+};
+
+template <typename... A>
+void pack_args(Launch& L, const A&... a) {
+    size_t off = 0;
+    auto add = [&](const void* p, size_t n) {
+        off = (off + 7) & ~size_t(7);
+        L.arg_offsets.push_back(off);
+        L.args.resize(off + n);
+        std::memcpy(L.args.data() + off, p, n);
+        off += n;
+    };
+    (add(&a, sizeof(A)), ...);
+}
+
+std::vector<void*> arg_pointers(Launch& L) {
+    std::vector<void*> p;
+    for (size_t o : L.arg_offsets) p.push_back(L.args.data() + o);
+    return p;
+}
+
+qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
+    if (ls.empty()) return QDP_OK;
+    if (!use_graph || ls.size() < 2) {
+        for (auto& L : ls) {
+            auto p = arg_pointers(L);
+            QDP_HIP(ctx, hipLaunchKernel(L.func, L.grid, L.block, p.data(), 0, ctx->stream));
+        }
+        return QDP_OK;
+    }
+    // Graph cache keyed by every launch's function, shape and argument bytes.
+    std::string key;
+    for (auto& L : ls) {
+        key.append(reinterpret_cast<const char*>(&L.func), sizeof(L.func));
+        key.append(reinterpret_cast<const char*>(&L.grid), sizeof(L.grid));
+        key.append(reinterpret_cast<const char*>(&L.block), sizeof(L.block));
+        key.append(L.args.data(), L.args.size());
+    }
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 16) {
+            auto victim = ctx->graphs.begin();
+            for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
+                if (g->second.last_use < victim->second.last_use) victim = g;
+            hipGraphExecDestroy(victim->second.exec);
+            ctx->graphs.erase(victim);
+        }
+        hipGraph_t graph;
+        QDP_HIP(ctx, hipGraphCreate(&graph, 0));
+        hipGraphNode_t prev = nullptr;
+        for (auto& L : ls) {
+            auto p = arg_pointers(L);
+            hipKernelNodeParams np{};
+            np.func = L.func;
+            np.gridDim = L.grid;
+            np.blockDim = L.block;
+            np.sharedMemBytes = 0;
+            np.kernelParams = p.data();
+            np.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            if (e != hipSuccess) {
+                hipGraphDestroy(graph);
+                return hip_error(ctx, e, "hipGraphAddKernelNode");
+            }
+            prev = node;
+        }
+        hipGraphExec_t exec;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_error(ctx, e, "hipGraphInstantiate");
+        it = ctx->graphs.emplace(key, GraphEntry{exec, 0}).first;
+    }
+    it->second.last_use = ++ctx->graph_tick;
+    QDP_HIP(ctx, hipGraphLaunch(it->second.exec, ctx->stream));
+    return QDP_OK;
+}
+
+// Occupancy variants compiled per precision (FP64 keeps the compiler's
+// choice: its links alone need 216 registers).
+template <int PREC>
+void* smear_func_occ(int occ) {
+    if constexpr (PREC == QDP_F64) {
+        return reinterpret_cast<void*>(&smear_kernel<PREC, 0>);
+    } else {
+        return occ == 3 ? reinterpret_cast<void*>(&smear_kernel<PREC, 3>)
+             : occ == 2 ? reinterpret_cast<void*>(&smear_kernel<PREC, 2>)
+                        : reinterpret_cast<void*>(&smear_kernel<PREC, 0>);
+    }
+}
+
+template <int PREC>
+void* smear_batch_func_occ(int occ) {
+    if constexpr (PREC == QDP_F64) {
+        return reinterpret_cast<void*>(&smear_batch_kernel<PREC, 0>);
+    } else {
+        return occ == 3 ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 3>)
+             : occ == 2 ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 2>)
+                        : reinterpret_cast<void*>(&smear_batch_kernel<PREC, 0>);
+    }
+}
+
+void* smear_func(int prec, int occ) {
+    switch (prec) {
+        case QDP_F64: return smear_func_occ<QDP_F64>(occ);
+        case QDP_F32: return smear_func_occ<QDP_F32>(occ);
+        default: return smear_func_occ<QDP_F16S>(occ);
+    }
+}
+
+void* smear_batch_func(int prec, int occ) {
+    switch (prec) {
+        case QDP_F64: return smear_batch_func_occ<QDP_F64>(occ);
+        case QDP_F32: return smear_batch_func_occ<QDP_F32>(occ);
+        default: return smear_batch_func_occ<QDP_F16S>(occ);
+    }
+}
+
+Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t count,
+                          const qdp_launch_shape& sh, double kappa) {
+    SmearLaunch ln{};
+    ln.site_begin = begin;
+    ln.site_count = count;
+    const int64_t tile_sites = 64LL * sh.site_waves;
+    ln.nlogical = (count + tile_sites - 1) / tile_sites;
+    ln.site_waves = sh.site_waves;
+    ln.col_groups = sh.col_groups;
+    ln.xcd = sh.xcd;
+    ln.kappa = kappa;
+    int64_t grid = ln.nlogical;
+    if (sh.xcd) grid = (grid + 7) / 8 * 8;
+    Launch L;
+    L.func = smear_func(prec, sh.waves_per_simd);
+    L.grid = dim3((unsigned)grid);
+    L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
+    pack_args(L, job, ln);
+    return L;
+}
+
+qdp_launch_shape default_shape() { return qdp_launch_shape{4, 1, 1, 2}; }
+
+// Validate a list of columns against the gauge field; returns precision and
+// lattice through the out arguments.
+qdp_status check_columns(Ctx* ctx, uint64_t gauge, const uint64_t* cols, int32_t ncols,
+                         uint64_t* lattice, int32_t* prec) {
+    Field* gf = find_field(ctx, gauge);
+    if (!gf) return set_error(ctx, QDP_ERR_STATE, "smear: unknown gauge handle");
+    if (gf->type != QDP_GAUGE) return set_error(ctx, QDP_ERR_TYPE, "smear: links must be a GAUGE field");
+    for (int32_t c = 0; c < ncols; ++c) {
+        Field* f = find_field(ctx, cols[c]);
+        if (!f) return set_error(ctx, QDP_ERR_STATE, "smear: unknown column handle");
+        if (f->type != QDP_FERMION) return set_error(ctx, QDP_ERR_TYPE, "smear: columns must be FERMION fields");
+        if (f->lattice != gf->lattice) return set_error(ctx, QDP_ERR_LATTICE, "smear: column on another lattice");
+        if (f->prec != gf->prec)
+            return set_error(ctx, QDP_ERR_UNSUPPORTED, "smear: column precision differs from the links'");
+    }
+    *lattice = gf->lattice;
+    *prec = gf->prec;
+    return QDP_OK;
+}
+
+qdp_status check_aliasing(Ctx* ctx, const uint64_t* src, const uint64_t* dst, int32_t ncols) {
+    for (int32_t a = 0; a < ncols; ++a)
+        for (int32_t b = 0; b < ncols; ++b) {
+            if (a == b) continue;
+            if (dst[a] == dst[b] || dst[a] == src[b])
+                return set_error(ctx, QDP_ERR_ALIAS, "smear: destination column %d aliases column %d", a, b);
+        }
+    return QDP_OK;
+}
+
+// Time one launch shape on the first pass (it writes only the buffer the
+// first real iteration overwrites).
+qdp_status time_shape(Ctx* ctx, int prec, const SmearJob& job, int64_t begin, int64_t count,
+                      const qdp_launch_shape& sh, double kappa, float* ms) {
+    Launch L = make_single_launch(prec, job, begin, count, sh, kappa);
+    auto p = arg_pointers(L);
+    hipEvent_t e0, e1;
+    QDP_HIP(ctx, hipEventCreate(&e0));
+    QDP_HIP(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        hipEventRecord(e0, ctx->stream);
+        hipLaunchKernel(L.func, L.grid, L.block, p.data(), 0, ctx->stream);
+        hipEventRecord(e1, ctx->stream);
+        hipError_t err = hipEventSynchronize(e1);
+        if (err != hipSuccess) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return hip_error(ctx, err, "autotune launch");
+        }
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        if (rep > 0) best = std::min(best, t);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = best;
+    return QDP_OK;
+}
+
+qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const SmearJob& job,
+                        int64_t begin, int64_t count, double kappa, qdp_launch_shape* out) {
+    if (ctx->forced.site_waves > 0) {
+        *out = ctx->forced;
+        return QDP_OK;
+    }
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) {
+        *out = it->second;
+        return QDP_OK;
+    }
+    qdp_launch_shape best = default_shape();
+    const int64_t work = count * job.ncols;
+    if (!(ctx->flags & QDP_INIT_NO_AUTOTUNE) && work >= (1 << 20)) {
+        float best_ms = 1e30f;
+        const int groups[] = {1, 2, 3, 4, 6};
+        for (int sw : {1, 2, 4})
+            for (int cg : groups) {
+                if (sw * cg > 4 || cg > job.ncols) continue;
+                for (int xcd : {0, 1})
+                    for (int occ : {0, 2, 3}) {
+                    if (prec == QDP_F64 && occ) continue;
+                    qdp_launch_shape sh{sw, cg, xcd, occ};
+                    float ms;
+                    QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = sh;
+                    }
+                }
+            }
+    }
+    ctx->tuned[key] = best;
+    *out = best;
+    return QDP_OK;
+}
+
+}  // namespace
+
+void release_graphs(Ctx* ctx) {
+    for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second.exec);
+    ctx->graphs.clear();
+}
+
+qdp_status smear_jacobi_impl(Ctx* ctx, uint64_t gauge, const uint64_t* src, const uint64_t* dst,
+                             int32_t ncols, double kappa, int32_t n_iter, int32_t j_decay,
+                             int32_t mode) {
+    if (ncols < 1 || ncols > 12) return set_error(ctx, QDP_ERR_ARG, "smear: 1..12 columns");
+    if (n_iter < 0) return set_error(ctx, QDP_ERR_ARG, "smear: negative iteration count");
+    if (!std::isfinite(kappa)) return set_error(ctx, QDP_ERR_ARG, "smear: kappa not finite");
+    if (j_decay != 3) return set_error(ctx, QDP_ERR_UNSUPPORTED, "smear: only j_decay = 3 (time)");
+    if (mode != QDP_SMEAR_FULL && mode != QDP_SMEAR_EVEN_ODD)
+        return set_error(ctx, QDP_ERR_ARG, "smear: unknown mode %d", mode);
+    uint64_t lat;
+    int32_t prec;
+    QDP_CHECK(check_columns(ctx, gauge, src, ncols, &lat, &prec));
+    QDP_CHECK(check_columns(ctx, gauge, dst, ncols, &lat, &prec));
+    QDP_CHECK(check_aliasing(ctx, src, dst, ncols));
+    const Geometry g = find_lattice(ctx, lat)->geo;
+
+    if (n_iter == 0) {
+        for (int32_t c = 0; c < ncols; ++c) {
+            if (src[c] == dst[c]) continue;
+            PinSet pins(ctx);
+            char *ps, *pd;
+            QDP_CHECK(pins.add(src[c], true, &ps));
+            QDP_CHECK(pins.add(dst[c], false, &pd));
+            QDP_HIP(ctx, hipMemcpyAsync(pd, ps, find_field(ctx, dst[c])->bytes, hipMemcpyDeviceToDevice,
+                                        ctx->stream));
+        }
+        return QDP_OK;
+    }
+
+    // Ping-pong partners: iteration k writes tmp for odd k and dst for even
+    // k; with an odd count the result lands in tmp and the storages of tmp
+    // and dst are exchanged afterwards.
+    std::vector<uint64_t> tmp(ncols, 0);
+    struct TmpGuard {
+        Ctx* ctx;
+        std::vector<uint64_t>* ids;
+        ~TmpGuard() {
+            for (uint64_t id : *ids)
+                if (id) field_destroy(ctx, id);
+        }
+    } guard{ctx, &tmp};
+    for (int32_t c = 0; c < ncols; ++c) QDP_CHECK(field_create(ctx, lat, QDP_FERMION, prec, &tmp[c]));
+
+    {
+        PinSet pins(ctx);
+        char* pg;
+        QDP_CHECK(pins.add(gauge, true, &pg));
+        std::vector<char*> ps(ncols), pd(ncols), pt(ncols);
+        for (int32_t c = 0; c < ncols; ++c) {
+            QDP_CHECK(pins.add(src[c], true, &ps[c]));
+            if (dst[c] != src[c]) QDP_CHECK(pins.add(dst[c], false, &pd[c]));
+            else pd[c] = ps[c];
+            QDP_CHECK(pins.add(tmp[c], false, &pt[c]));
+        }
+
+        SmearJob first{}, to_dst{}, to_tmp{};
+        first.g = to_dst.g = to_tmp.g = g;
+        first.gauge = to_dst.gauge = to_tmp.gauge = pg;
+        first.ncols = to_dst.ncols = to_tmp.ncols = ncols;
+        for (int32_t c = 0; c < ncols; ++c) {
+            first.src[c] = ps[c];
+            first.dst[c] = pt[c];
+            to_dst.src[c] = pt[c];
+            to_dst.dst[c] = pd[c];
+            to_tmp.src[c] = pd[c];
+            to_tmp.dst[c] = pt[c];
+        }
+
+        struct Pass {
+            int64_t begin, count;
+        };
+        std::vector<Pass> passes;
+        if (mode == QDP_SMEAR_FULL) passes.push_back({0, g.V});
+        else {
+            passes.push_back({0, g.Vh});
+            passes.push_back({g.Vh, g.Vh});
+        }
+
+        SmearTuneKey key{{g.L[0], g.L[1], g.L[2], g.L[3]}, ncols, prec, mode, 0};
+        qdp_launch_shape sh;
+        QDP_CHECK(choose_shape(ctx, key, prec, first, passes[0].begin, passes[0].count, kappa, &sh));
+        ctx->last_shape = sh;
+
+        std::vector<Launch> ls;
+        for (int32_t k = 1; k <= n_iter; ++k) {
+            const SmearJob& job = k == 1 ? first : (k % 2 == 0 ? to_dst : to_tmp);
+            for (const Pass& p : passes) ls.push_back(make_single_launch(prec, job, p.begin, p.count, sh, kappa));
+        }
+        QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH)));
+        QDP_CHECK(check_launch(ctx, "smear kernel"));
+    }
+    if (n_iter % 2 == 1) {
+        for (int32_t c = 0; c < ncols; ++c)
+            if (ctx->cache.swap_storage(dst[c], tmp[c]) != QDP_OK)
+                return set_error(ctx, QDP_ERR_STATE, "smear: result hand-over failed");
+    }
+    return QDP_OK;
+}
+
+qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, double kappa,
+                            int32_t n_iter) {
+    if (n_iter < 0) return set_error(ctx, QDP_ERR_ARG, "smear batch: negative iteration count");
+    if (!std::isfinite(kappa)) return set_error(ctx, QDP_ERR_ARG, "smear batch: kappa not finite");
+    int32_t prec = -1;
+    std::vector<std::vector<uint64_t>> src(njobs), dst(njobs);
+    std::vector<uint64_t> lats(njobs);
+    for (int32_t j = 0; j < njobs; ++j) {
+        const qdp_smear_job& J = jobs[j];
+        if (!J.src || !J.dst || J.ncols < 1 || J.ncols > 12)
+            return set_error(ctx, QDP_ERR_ARG, "smear batch: job %d needs 1..12 columns", j);
+        src[j].assign(J.src, J.src + J.ncols);
+        dst[j].assign(J.dst, J.dst + J.ncols);
+        int32_t p;
+        QDP_CHECK(check_columns(ctx, J.gauge, src[j].data(), J.ncols, &lats[j], &p));
+        QDP_CHECK(check_columns(ctx, J.gauge, dst[j].data(), J.ncols, &lats[j], &p));
+        QDP_CHECK(check_aliasing(ctx, src[j].data(), dst[j].data(), J.ncols));
+        if (prec >= 0 && p != prec)
+            return set_error(ctx, QDP_ERR_UNSUPPORTED, "smear batch: all jobs must share one precision");
+        prec = p;
+    }
+    for (int32_t a = 0; a < njobs; ++a)
+        for (int32_t b = a + 1; b < njobs; ++b)
+            for (uint64_t x : dst[a])
+                for (int32_t c = 0; c < jobs[b].ncols; ++c)
+                    if (x == dst[b][c] || x == src[b][c])
+                        return set_error(ctx, QDP_ERR_ALIAS, "smear batch: jobs %d and %d share a field", a, b);
+    if (n_iter == 0) {
+        for (int32_t j = 0; j < njobs; ++j)
+            QDP_CHECK(smear_jacobi_impl(ctx, jobs[j].gauge, src[j].data(), dst[j].data(), jobs[j].ncols,
+                                        kappa, 0, 3, QDP_SMEAR_FULL));
+        return QDP_OK;
+    }
+
+    std::vector<std::vector<uint64_t>> tmp(njobs);
+    struct TmpGuard {
+        Ctx* ctx;
+        std::vector<std::vector<uint64_t>>* ids;
+        ~TmpGuard() {
+            for (auto& v : *ids)
+                for (uint64_t id : v)
+                    if (id) field_destroy(ctx, id);
+        }
+    } guard{ctx, &tmp};
+    for (int32_t j = 0; j < njobs; ++j) {
+        tmp[j].assign(jobs[j].ncols, 0);
+        for (int32_t c = 0; c < jobs[j].ncols; ++c)
+            QDP_CHECK(field_create(ctx, lats[j], QDP_FERMION, prec, &tmp[j][c]));
+    }
+
+    qdp_launch_shape sh = ctx->forced.site_waves > 0 ? ctx->forced : default_shape();
+    ctx->last_shape = sh;
+    const int64_t tile_sites = 64LL * sh.site_waves;
+
+    PinSet pins(ctx);
+    std::vector<SmearJob> h_first(njobs), h_dst(njobs), h_tmp(njobs);
+    std::vector<int64_t> h_tiles(njobs + 1, 0);
+    for (int32_t j = 0; j < njobs; ++j) {
+        const Geometry& g = find_lattice(ctx, lats[j])->geo;
+        char* pg;
+        QDP_CHECK(pins.add(jobs[j].gauge, true, &pg));
+        SmearJob a{}, b{}, c{};
+        a.g = b.g = c.g = g;
+        a.gauge = b.gauge = c.gauge = pg;
+        a.ncols = b.ncols = c.ncols = jobs[j].ncols;
+        for (int32_t k = 0; k < jobs[j].ncols; ++k) {
+            char *ps, *pd, *pt;
+            QDP_CHECK(pins.add(src[j][k], true, &ps));
+            if (dst[j][k] != src[j][k]) QDP_CHECK(pins.add(dst[j][k], false, &pd));
+            else pd = ps;
+            QDP_CHECK(pins.add(tmp[j][k], false, &pt));
+            a.src[k] = ps;
+            a.dst[k] = pt;
+            b.src[k] = pt;
+            b.dst[k] = pd;
+            c.src[k] = pd;
+            c.dst[k] = pt;
+        }
+        h_first[j] = a;
+        h_dst[j] = b;
+        h_tmp[j] = c;
+        h_tiles[j + 1] = h_tiles[j] + (g.V + tile_sites - 1) / tile_sites;
+    }
+    const size_t jb = sizeof(SmearJob) * njobs;
+    const size_t tb = sizeof(int64_t) * (njobs + 1);
+    PoolTemp dev;
+    QDP_CHECK(dev.alloc(ctx, (int64_t)(3 * jb + tb + 1024)));
+    char* d_first = dev.ptr();
+    char* d_dst = d_first + ((jb + 255) & ~size_t(255));
+    char* d_tmp = d_dst + ((jb + 255) & ~size_t(255));
+    char* d_tiles = d_tmp + ((jb + 255) & ~size_t(255));
+    QDP_HIP(ctx, hipMemcpyAsync(d_first, h_first.data(), jb, hipMemcpyHostToDevice, ctx->stream));
+    QDP_HIP(ctx, hipMemcpyAsync(d_dst, h_dst.data(), jb, hipMemcpyHostToDevice, ctx->stream));
+    QDP_HIP(ctx, hipMemcpyAsync(d_tmp, h_tmp.data(), jb, hipMemcpyHostToDevice, ctx->stream));
+    QDP_HIP(ctx, hipMemcpyAsync(d_tiles, h_tiles.data(), tb, hipMemcpyHostToDevice, ctx->stream));
+
+    SmearLaunch ln{};
+    ln.site_waves = sh.site_waves;
+    ln.col_groups = sh.col_groups;
+    ln.xcd = sh.xcd;
+    ln.kappa = kappa;
+    const int64_t ntiles = h_tiles[njobs];
+    int64_t grid = std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * 8);
+    grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
+    std::vector<Launch> ls;
+    for (int32_t k = 1; k <= n_iter; ++k) {
+        const SmearJob* J = reinterpret_cast<const SmearJob*>(k == 1 ? d_first : (k % 2 == 0 ? d_dst : d_tmp));
+        const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles);
+        Launch L;
+        L.func = smear_batch_func(prec, sh.waves_per_simd);
+        L.grid = dim3((unsigned)grid);
+        L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
+        pack_args(L, J, T, njobs, ln);
+        ls.push_back(std::move(L));
+    }
+    QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH)));
+    QDP_CHECK(check_launch(ctx, "smear batch kernel"));
+    if (n_iter % 2 == 1) {
+        for (int32_t j = 0; j < njobs; ++j)
+            for (int32_t c = 0; c < jobs[j].ncols; ++c)
+                if (ctx->cache.swap_storage(dst[j][c], tmp[j][c]) != QDP_OK)
+                    return set_error(ctx, QDP_ERR_STATE, "smear batch: result hand-over failed");
+    }
+    return QDP_OK;
+}
+
+}  // namespace qdpmi

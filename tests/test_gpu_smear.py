@@ -1,0 +1,216 @@
+"""GPU parity: Jacobi smearing through the C ABI against the FP64 oracle.
+
+Tolerances (relative L2 over the whole field, a reference zero must stay an
+exact zero): FP64 1e-12, FP32 1e-5, F16S 2e-3.  Free-field cases with
+kappa = 1/4 are exact rationals and must match bitwise (FP64 for N <= 15,
+FP32 for N <= 7).  Launch shapes, even/odd passes, graph replay and the
+multi-lattice kernel must agree bitwise with each other."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_5596_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"F64": 1e-12, "F32": 1e-5, "F16S": 2e-3}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def upload(q, dims, U, cols, prec):
+    lat = q.lattice(dims)
+    g = q.alloc(lat, "GAUGE", prec)
+    q.write(g, U)
+    fs = []
+    for c in cols:
+        f = q.alloc(lat, "FERMION", prec)
+        q.write(f, c)
+        fs.append(f)
+    return lat, g, fs
+
+
+def free_all(q, fields):
+    for f in fields:
+        q.free(f)
+
+
+def unit_links(dims):
+    U = np.zeros((4, synth.volume(dims), 3, 3), dtype=np.complex128)
+    U[:] = np.eye(3)
+    return U
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_plain_method_4cubed(qdp, prec):
+    """4^3 x 8, Haar links seed 1, point source column 0, kappa 0.25, N 10."""
+    dims = (4, 4, 4, 8)
+    U = synth.su3_links(dims, 1)
+    src = synth.point_source(dims, [0])
+    expect = oracle.smear(U, src, dims, 0.25, 10)[0]
+    lat, g, (f,) = upload(qdp, dims, U, src, prec)
+    qdp.smear(g, [f], 0.25, 10)
+    got = qdp.read(f)
+    assert rel(got, expect) <= TOL[prec]
+    # pion correlator C(t) = sum_x |psi(x, t)|^2 via the FP64 time-slice sums
+    corr = qdp.sum_multi([("field", f), ("local_norm2",)], "timeslice", 1, dims[3])[:, 0].real
+    ref = oracle.timeslice_sum(np.sum(np.abs(expect) ** 2, axis=(1, 2)), dims)[:, 0].real
+    assert np.count_nonzero(corr[1:]) == 0
+    assert abs(corr[0] - ref[0]) <= TOL[prec] * ref[0]
+    free_all(qdp, [g, f])
+
+
+@pytest.mark.parametrize("prec,n", [("F64", 10), ("F64", 15), ("F32", 7)])
+def test_free_field_bitwise(qdp, prec, n):
+    dims = (4, 4, 4, 8)
+    U = unit_links(dims)
+    src = synth.point_source(dims, [0, 5])
+    expect = oracle.smear(U, src, dims, 0.25, n)
+    lat, g, fs = upload(qdp, dims, U, src, prec)
+    qdp.smear(g, fs, 0.25, n, mode=1)
+    for c in range(2):
+        assert np.array_equal(qdp.read(fs[c]), expect[c])
+    free_all(qdp, [g] + fs)
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16S"])
+@pytest.mark.parametrize("dims,ncols,n", [((8, 8, 8, 4), 12, 9), ((6, 4, 10, 2), 5, 6),
+                                          ((2, 2, 2, 2), 12, 10)])
+def test_random_links_multi_column(qdp, prec, dims, ncols, n):
+    U = synth.su3_links(dims, 7)
+    psi = synth.gaussian_propagator(dims, 107, ncols=ncols)
+    expect = oracle.smear(U, psi, dims, 0.25, n)
+    lat, g, fs = upload(qdp, dims, U, psi, prec)
+    qdp.smear(g, fs, 0.25, n)
+    for c in range(ncols):
+        assert rel(qdp.read(fs[c]), expect[c]) <= TOL[prec], (prec, c)
+    free_all(qdp, [g] + fs)
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16S"])
+def test_even_odd_equals_full_bitwise(qdp, prec):
+    dims = (8, 4, 6, 4)
+    U = synth.su3_links(dims, 3)
+    psi = synth.gaussian_propagator(dims, 103, ncols=12)
+    lat, g, a = upload(qdp, dims, U, psi, prec)
+    b = []
+    for c in psi:
+        f = qdp.alloc(lat, "FERMION", prec)
+        qdp.write(f, c)
+        b.append(f)
+    qdp.smear(g, a, 0.25, 7, mode=0)
+    qdp.smear(g, b, 0.25, 7, mode=1)
+    for x, y in zip(a, b):
+        assert np.array_equal(qdp.read(x), qdp.read(y))
+    free_all(qdp, [g] + a + b)
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16S"])
+def test_launch_shapes_bitwise(qdp, prec):
+    dims = (8, 8, 4, 4)
+    U = synth.su3_links(dims, 4)
+    psi = synth.gaussian_propagator(dims, 104, ncols=12)
+    lat, g, fs = upload(qdp, dims, U, psi, prec)
+    out = qdp.alloc(lat, "FERMION", prec)
+    ref = None
+    try:
+        for sw, cg, xcd, occ in [(1, 1, 0, 0), (4, 1, 1, 2), (2, 2, 1, 3), (1, 3, 0, 2), (1, 4, 1, 0),
+                                 (2, 1, 0, 3)]:
+            qdp.set_shape(sw, cg, xcd, occ)
+            outs = [qdp.alloc(lat, "FERMION", prec) for _ in fs]
+            qdp.smear_to(g, fs, outs, 0.25, 5, mode=1)
+            assert qdp.get_shape() == (sw, cg, xcd, occ)
+            vals = [qdp.read(o) for o in outs]
+            if ref is None:
+                ref = vals
+            for v, r in zip(vals, ref):
+                assert np.array_equal(v, r)
+            free_all(qdp, outs)
+    finally:
+        qdp.set_shape(0)
+    # inputs untouched by the out-of-place call
+    for f, c in zip(fs, psi):
+        if prec == "F32":
+            assert np.array_equal(qdp.read(f), c.astype(np.complex64).astype(np.complex128))
+    free_all(qdp, [g, out] + fs)
+
+
+def test_graph_replay_equals_eager(qdp):
+    from paper_1111_5596_amd import qdpmi
+
+    dims = (8, 4, 4, 4)
+    U = synth.su3_links(dims, 5)
+    psi = synth.gaussian_propagator(dims, 105, ncols=3)
+    eager = qdpmi.Context(pool_bytes=1 << 30, flags=qdpmi.INIT_NO_GRAPH | qdpmi.INIT_NO_AUTOTUNE)
+    try:
+        res = []
+        for q in (qdp, eager):
+            lat, g, fs = upload(q, dims, U, psi, "F32")
+            for rep in range(3):  # replays of the cached graph
+                q.smear(g, fs, 0.25, 4)
+            res.append([q.read(f) for f in fs])
+            free_all(q, [g] + fs)
+        for a, b in zip(*res):
+            assert np.array_equal(a, b)
+    finally:
+        eager.close()
+
+
+def test_batch_equals_single_bitwise(qdp):
+    sizes = [(4, 4, 4, 8), (6, 6, 6, 4), (8, 4, 4, 2), (4, 4, 4, 8)]
+    jobs, single, expect = [], [], []
+    for j, dims in enumerate(sizes):
+        U = synth.su3_links(dims, 4001 + j)
+        src = synth.point_source(dims, range(12))
+        lat, g, fs = upload(qdp, dims, U, src, "F32")
+        _, g2, fs2 = upload(qdp, dims, U, src, "F32")
+        jobs.append((g, fs, fs))
+        single.append((g2, fs2))
+        expect.append(oracle.smear(U, src[:2], dims, 0.25, 9))
+    qdp.smear_batch(jobs, 0.25, 9)
+    for (g2, fs2) in single:
+        qdp.smear(g2, fs2, 0.25, 9)
+    for (g, fs, _), (g2, fs2), ex in zip(jobs, single, expect):
+        for c in range(12):
+            assert np.array_equal(qdp.read(fs[c]), qdp.read(fs2[c]))
+        for c in range(2):
+            assert rel(qdp.read(fs[c]), ex[c]) <= 1e-5
+        free_all(qdp, [g, g2] + fs + fs2)
+
+
+def test_zero_iterations_copies(qdp):
+    dims = (4, 4, 2, 2)
+    psi = synth.gaussian_propagator(dims, 9, ncols=2)
+    lat, g, fs = upload(qdp, dims, synth.su3_links(dims, 9), psi, "F64")
+    outs = [qdp.alloc(lat, "FERMION", "F64") for _ in fs]
+    qdp.smear_to(g, fs, outs, 0.25, 0)
+    for o, c in zip(outs, psi):
+        assert np.array_equal(qdp.read(o), c)
+    free_all(qdp, [g] + fs + outs)
+
+
+def test_smear_errors(qdp):
+    from paper_1111_5596_amd.qdpmi import QdpError
+
+    dims = (4, 4, 4, 4)
+    lat = qdp.lattice(dims)
+    g = qdp.alloc(lat, "GAUGE", "F32")
+    f = qdp.alloc(lat, "FERMION", "F32")
+    h = qdp.alloc(lat, "FERMION", "F64")
+    other = qdp.alloc(qdp.lattice((4, 4, 4, 2)), "FERMION", "F32")
+    with pytest.raises(QdpError, match="UNSUPPORTED"):
+        qdp.smear(g, [h], 0.25, 1)
+    with pytest.raises(QdpError, match="LATTICE"):
+        qdp.smear(g, [other], 0.25, 1)
+    with pytest.raises(QdpError, match="TYPE"):
+        qdp.smear(f, [f], 0.25, 1)
+    with pytest.raises(QdpError, match="UNSUPPORTED"):
+        qdp.smear(g, [f], 0.25, 1, j_decay=2)
+    with pytest.raises(QdpError, match="ALIAS"):
+        qdp.smear(g, [f, f], 0.25, 1)
+    with pytest.raises(QdpError, match="ARG"):
+        qdp.smear(g, [f], 0.25, -1)
+    free_all(qdp, [g, f, h, other])
