@@ -375,8 +375,9 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
  * column groups = col_groups (each thread updates ceil(ncols / col_groups)
  * columns of one site), xcd = 1 maps consecutive blocks to one XCD,
  * waves_per_simd selects the kernel variant compiled for that occupancy
- * (0, 2 or 3; 0 = compiler default; FP64 always uses 0).  Every shape
- * computes bitwise-identical results.  qdp_smear_set_shape forces a
+ * (0, 2 or 3; 0 = compiler default; FP64 always uses 0), flat = 1 uses
+ * 64-bit flat addresses instead of buffer addressing (forced on when a field
+ * is 4 GiB or larger).  Every shape computes bitwise-identical results.  qdp_smear_set_shape forces a
  * shape (site_waves = 0 returns to autotuning); qdp_smear_get_shape reports
  * the shape the last smearing call used. */
 typedef struct {
@@ -384,6 +385,8 @@ typedef struct {
     int32_t col_groups;
     int32_t xcd;
     int32_t waves_per_simd;
+    int32_t flat;
+    int32_t reserved;
 } qdp_launch_shape;
 qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape);
 qdp_status qdp_smear_get_shape(qdp_ctx* ctx, qdp_launch_shape* out);

@@ -1,20 +1,23 @@
 // Lattice geometry, lattice-object types and the device storage layout,
 // shared by the host runtime and the kernels.
 //
-// Device layout (structure of arrays, checkerboard site order):
+// Device layout: checkerboard site order, 64-site tiles.
 //   cb(x, y, z, t) = p * V/2 + (x/2) + (Lx/2) * (y + Ly * (z + Lz * t)),
 //   p = (x + y + z + t) mod 2,
 // so the even sites come first, each parity half is ordered like the
 // lexicographic order with x halved, and a time slice is a contiguous range
-// of Vs/2 sites in each half.  A field is nrec records per site (4 colour
-// matrices for a gauge field, 1 otherwise) of ncomp complex components;
-// component k of record r is one plane of `plane` sites:
-//   F64   double2 planes                      16 B per complex
-//   F32   float2 planes                        8 B per complex
-//   F16S  half2 planes, then nrec float scale planes (one scale per record)
-// The paper's GPU kernels used uncoalesced per-site layouts (section 6);
-// with this layout consecutive lanes of a wavefront read consecutive 8-byte
-// (4-byte) words.
+// of Vs/2 sites in each half.  Sites are grouped in tiles of 64 consecutive
+// checkerboard sites (one wavefront); a tile stores, for each of its rows, the
+// 64 sites' values of one component, one row after the other:
+//   row r*ncomp + k  component k of record r (nrec records of ncomp complex)
+//   F64   double2 elements  (1024-byte rows)
+//   F32   float2 elements   ( 512-byte rows)
+//   F16S  half2 elements    ( 256-byte rows), then nrec rows of FP32 record
+//         scales
+// Lanes of a wavefront read consecutive elements of a row (coalesced), and all
+// the components of a site block sit in one contiguous tile, so a wavefront
+// touches one memory page per neighbouring tile instead of one per component
+// plane (the paper's kernels used uncoalesced per-site records, section 6).
 #pragma once
 
 #include <cstddef>
@@ -65,7 +68,7 @@ struct Geometry {
     int64_t V;      // sites
     int64_t Vh;     // V / 2
     int64_t Vsh;    // sites per time slice per parity = Lx Ly Lz / 2
-    int64_t plane;  // plane stride in sites (V rounded up to 64)
+    int64_t plane;  // allocated sites: V rounded up to a whole number of 64-site tiles
 };
 
 inline Geometry make_geometry(const int32_t d[4]) {
@@ -80,23 +83,33 @@ inline Geometry make_geometry(const int32_t d[4]) {
     return g;
 }
 
+// Bytes of one 64-site tile of a field.
+QDP_HD inline int64_t tile_bytes(int32_t nrec, int32_t ncomp, int32_t prec) {
+    return 64 * ((int64_t)nrec * ncomp * prec_complex_bytes(prec) + (prec == QDP_F16S ? 4 * (int64_t)nrec : 0));
+}
+
 // Device bytes of a field.
 inline int64_t field_bytes(const Geometry& g, int32_t type, int32_t prec) {
     const TypeShape s = type_shape(type);
-    int64_t b = (int64_t)s.nrec * s.ncomp * g.plane * prec_complex_bytes(prec);
-    if (prec == QDP_F16S) b += (int64_t)s.nrec * g.plane * 4;
-    return b;
+    return g.plane / 64 * tile_bytes(s.nrec, s.ncomp, prec);
 }
 
-// Offset in bytes of component plane (rec, comp).
-QDP_HD inline int64_t plane_offset(int64_t plane, int32_t ncomp, int32_t prec, int32_t rec,
-                                   int32_t comp) {
-    return ((int64_t)rec * ncomp + comp) * plane * prec_complex_bytes(prec);
+// Byte offset of row 0 of site `site` (elements of `esize` bytes) in a field
+// whose tiles are `tb` bytes.
+QDP_HD inline int64_t tile_site_offset(int64_t tb, int64_t esize, int64_t site) {
+    return (site >> 6) * tb + (site & 63) * esize;
 }
 
-// Offset in bytes of the F16S scale plane of record rec.
-QDP_HD inline int64_t scale_offset(int64_t plane, int32_t nrec, int32_t ncomp, int32_t rec) {
-    return (int64_t)nrec * ncomp * plane * 4 + (int64_t)rec * plane * 4;
+// Byte offset of component k of record rec at `site`.
+QDP_HD inline int64_t comp_offset(int32_t nrec, int32_t ncomp, int32_t prec, int32_t rec, int32_t comp,
+                                  int64_t site) {
+    const int64_t es = prec_complex_bytes(prec);
+    return tile_site_offset(tile_bytes(nrec, ncomp, prec), es, site) + ((int64_t)rec * ncomp + comp) * 64 * es;
+}
+
+// Byte offset of the F16S scale of record rec at `site`.
+QDP_HD inline int64_t scale_offset(int32_t nrec, int32_t ncomp, int32_t rec, int64_t site) {
+    return tile_site_offset(tile_bytes(nrec, ncomp, QDP_F16S), 4, site) + ((int64_t)nrec * ncomp + rec) * 64 * 4;
 }
 
 // Checkerboard index of lexicographic coordinates.

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
@@ -41,38 +42,31 @@ struct ContractArgs {
     int32_t pad;
 };
 
+// Load one 12-component column at checkerboard site s; FP32 and F16S values
+// are returned as float2 (F16S decoded with its record scale), FP64 as
+// double2.  Products are formed in FP64 by the caller.
 template <int PREC>
-__device__ __forceinline__ void load_column(const char* base, int64_t plane, int32_t s, double2 v[12]) {
-    if constexpr (PREC == QDP_F64) {
-        const double2* p = reinterpret_cast<const double2*>(base);
+using ColT = typename std::conditional<PREC == QDP_F64, double2, float2>::type;
+
+template <int PREC, bool BUF>
+__device__ __forceinline__ void load_column(const char* base, int32_t s, ColT<PREC> v[12]) {
+    if constexpr (PREC == QDP_F16S) {
+        const FieldRef<half2_t, BUF> f(base);
+        const FieldRef<float, BUF> sc(base);
+        const int64_t so = site_off<half2_t>(s, tile_bytes(1, 12, QDP_F16S));
+        const float scale = sc.load(12, so);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = p[(int64_t)k * plane + s];
-    } else if constexpr (PREC == QDP_F32) {
-        const float2* p = reinterpret_cast<const float2*>(base);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const float2 f = p[(int64_t)k * plane + s];
-            v[k] = make_double2(f.x, f.y);
-        }
+        for (int k = 0; k < 12; ++k) v[k] = f16s_decode(f.load(k, so), scale);
     } else {
-        const half2_t* p = reinterpret_cast<const half2_t*>(base);
-        const double sc = reinterpret_cast<const float*>(base + scale_offset(plane, 1, 12, 0))[s];
+        const FieldRef<ColT<PREC>, BUF> f(base);
+        const int64_t so = site_off<ColT<PREC>>(s, tile_bytes(1, 12, PREC));
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const half2_t h = p[(int64_t)k * plane + s];
-            v[k] = make_double2((double)(float)h.x * sc, (double)(float)h.y * sc);
-        }
+        for (int k = 0; k < 12; ++k) v[k] = f.load(k, so);
     }
 }
 
-__device__ __forceinline__ double2 phase_mul(int code, double2 z) {
-    switch (code & 3) {
-        case 0: return z;
-        case 1: return make_double2(-z.y, z.x);
-        case 2: return make_double2(-z.x, -z.y);
-        default: return make_double2(z.y, -z.x);
-    }
-}
+__device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d(double2 v) { return v; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -80,59 +74,68 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd) {
-    const int t = blockIdx.y;
-    const int chunk = blockIdx.x;
-    const int sigma = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t Vsh = a.g.Vsh;
+// i^code as (re, im), code mod 4.
+__device__ __forceinline__ double2 unit_phase(int code) {
+    code &= 3;
+    return make_double2(code == 0 ? 1.0 : (code == 2 ? -1.0 : 0.0), code == 1 ? 1.0 : (code == 3 ? -1.0 : 0.0));
+}
+
+// Sites of one slice chunk for the Klein-group element SIGMA (spin
+// permutation a -> a ^ SIGMA).  The source spin beta is the outer loop so
+// only one column of G and the four correlators stay in registers.
+template <int PREC, bool BUF, int SIGMA>
+__device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDev& gd, int t, int chunk, int lane,
+                                            double2 C[4]) {
+    const int64_t Vsh = A.g.Vsh;
     const int64_t Vs = 2 * Vsh;
-    const int64_t plane = a.g.plane;
-    int perm[4];
+    int n[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) perm[i] = gd.perm[sigma][i];
-
-    double2 C[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) C[m] = make_double2(0.0, 0.0);
-
-    for (int64_t l = (int64_t)chunk * 64 + lane; l < Vs; l += (int64_t)a.nchunks * 64) {
+    for (int m = 0; m < 4; ++m) n[m] = gd.members[SIGMA][m];
+    for (int64_t l = (int64_t)chunk * 64 + lane; l < Vs; l += (int64_t)A.nchunks * 64) {
         const int64_t p = l >= Vsh ? 1 : 0;
-        const int32_t s = (int32_t)(p * a.g.Vh + t * Vsh + (l - p * Vsh));
-        double2 G[4][4];
+        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int beta = 0; beta < 4; ++beta) {
+            double2 G[4];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) G[x][y] = make_double2(0.0, 0.0);
+            for (int x = 0; x < 4; ++x) G[x] = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int beta = 0; beta < 4; ++beta) {
-                double2 c2[12], c1[12];
-                load_column<PREC>(a.s2[3 * beta + b], plane, s, c2);
-                load_column<PREC>(a.s1[3 * perm[beta] + b], plane, s, c1);
+            for (int b = 0; b < 3; ++b) {
+                ColT<PREC> c2[12], c1[12];
+                load_column<PREC, BUF>(A.s2[3 * beta + b], s, c2);
+                load_column<PREC, BUF>(A.s1[3 * (beta ^ SIGMA) + b], s, c1);
 #pragma unroll
                 for (int alpha = 0; alpha < 4; ++alpha)
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        cmac_conj(G[alpha][beta], c2[3 * alpha + c], c1[3 * perm[alpha] + c]);
+                        cmac_conj(G[alpha], to_d(c2[3 * alpha + c]), to_d(c1[3 * (alpha ^ SIGMA) + c]));
             }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int n = gd.members[sigma][m];
-            double2 acc = make_double2(0.0, 0.0);
+            for (int m = 0; m < 4; ++m) {
 #pragma unroll
-            for (int alpha = 0; alpha < 4; ++alpha)
-#pragma unroll
-                for (int beta = 0; beta < 4; ++beta) {
-                    const double2 z = phase_mul(gd.pcode[n][alpha] + gd.qcode[n][beta], G[alpha][beta]);
-                    acc.x += z.x;
-                    acc.y += z.y;
+                for (int alpha = 0; alpha < 4; ++alpha) {
+                    const double2 ph = unit_phase(gd.pcode[n[m]][alpha] + gd.qcode[n[m]][beta]);
+                    cmac(C[m], ph, G[alpha]);
                 }
-            C[m].x += acc.x;
-            C[m].y += acc.y;
+            }
         }
+    }
+}
+
+template <int PREC, bool BUF>
+__global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd) {
+    const int t = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int sigma = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double2 C[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) C[m] = make_double2(0.0, 0.0);
+    switch (sigma) {
+        case 0: meson_sites<PREC, BUF, 0>(a, gd, t, chunk, lane, C); break;
+        case 1: meson_sites<PREC, BUF, 1>(a, gd, t, chunk, lane, C); break;
+        case 2: meson_sites<PREC, BUF, 2>(a, gd, t, chunk, lane, C); break;
+        default: meson_sites<PREC, BUF, 3>(a, gd, t, chunk, lane, C); break;
     }
     __shared__ double red[4][4][2];
 #pragma unroll
@@ -235,13 +238,16 @@ int phase_code(const double ph[2]) {
     return 3;
 }
 
-void* meson_func(int prec) {
+template <bool BUF>
+void* meson_func_buf(int prec) {
     switch (prec) {
-        case QDP_F64: return reinterpret_cast<void*>(&meson_kernel<QDP_F64>);
-        case QDP_F32: return reinterpret_cast<void*>(&meson_kernel<QDP_F32>);
-        default: return reinterpret_cast<void*>(&meson_kernel<QDP_F16S>);
+        case QDP_F64: return reinterpret_cast<void*>(&meson_kernel<QDP_F64, BUF>);
+        case QDP_F32: return reinterpret_cast<void*>(&meson_kernel<QDP_F32, BUF>);
+        default: return reinterpret_cast<void*>(&meson_kernel<QDP_F16S, BUF>);
     }
 }
+
+void* meson_func(int prec, bool buf) { return buf ? meson_func_buf<true>(prec) : meson_func_buf<false>(prec); }
 }  // namespace
 
 qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
@@ -263,7 +269,7 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
     const Geometry g = find_lattice(ctx, lat)->geo;
     const int32_t Lt = g.L[3];
     const int64_t Vs = 2 * g.Vsh;
-    int64_t nchunks = (2048 + Lt - 1) / Lt;
+    int64_t nchunks = (8192 + Lt - 1) / Lt;
     nchunks = std::max<int64_t>(1, std::min<int64_t>(nchunks, (Vs + 63) / 64));
 
     PinSet pins(ctx);
@@ -297,7 +303,8 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
         }
 
     void* args[] = {&a, &gd};
-    QDP_HIP(ctx, hipLaunchKernel(meson_func(prec), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256), args, 0,
+    const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
+    QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256), args, 0,
                                  ctx->stream));
     QDP_CHECK(check_launch(ctx, "meson kernel"));
     const int nthreads = 16 * Lt;

@@ -65,6 +65,124 @@ __device__ __forceinline__ float2 f16s_decode(half2_t q, float scale) {
     return make_float2((float)q.x * scale, (float)q.y * scale);
 }
 
+// Raw buffer access: one 128-bit resource per field (base address, no
+// stride, full 32-bit range), a per-lane byte offset in a VGPR shared by all
+// component planes, and the plane offset as a uniform (SGPR) operand.  This
+// removes the 64-bit address arithmetic a flat load needs for every plane.
+// Requires every accessed offset of the field to be below 4 GiB.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// `p` must be the same for every lane of the wavefront (true for all the
+// field bases the kernels address): it is read from the first lane so the
+// resource lives in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    void* u = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+    // word 3: 32-bit data format, the setting used for raw buffers on gfx9
+    return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, -1, 0x00020000);
+}
+
+__device__ __forceinline__ half2_t buf_load_h2(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(half2_t, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ float2 buf_load_c32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ double2 buf_load_c64(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void buf_store_h2(half2_t v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void buf_store_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void buf_store_c32(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void buf_store_c64(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, (int)vo, (int)so, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so);
+template <>
+__device__ __forceinline__ float2 bload<float2>(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return buf_load_c32(r, vo, so);
+}
+template <>
+__device__ __forceinline__ double2 bload<double2>(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return buf_load_c64(r, vo, so);
+}
+template <>
+__device__ __forceinline__ half2_t bload<half2_t>(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return buf_load_h2(r, vo, so);
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return buf_load_f32(r, vo, so);
+}
+__device__ __forceinline__ void bstore(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    buf_store_c32(v, r, vo, so);
+}
+__device__ __forceinline__ void bstore(double2 v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    buf_store_c64(v, r, vo, so);
+}
+__device__ __forceinline__ void bstore(half2_t v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    buf_store_h2(v, r, vo, so);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    buf_store_f32(v, r, vo, so);
+}
+
+// Access to the rows of a tiled field (see common.hpp).  `so` is the byte
+// offset of a site in row 0, tile_site_offset(tile bytes, sizeof(T), site);
+// row r of that site is r * 64 * sizeof(T) bytes further.  The buffer path
+// keeps one 32-bit per-lane offset per site and turns the row offsets into
+// instruction immediates (needs the field below 4 GiB, checked on the host);
+// the flat path uses 64-bit addresses.
+template <typename T, bool BUF>
+struct FieldRef {
+    const char* base;
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ explicit FieldRef(const char* p) : base(p) {
+        if constexpr (BUF) rsrc = buffer_rsrc(p);
+    }
+    __device__ __forceinline__ T load(int row, int64_t so) const {
+        if constexpr (BUF)
+            return bload<T>(rsrc, (uint32_t)so + (uint32_t)(row * 64 * (int)sizeof(T)), 0u);
+        else
+            return *reinterpret_cast<const T*>(base + so + (int64_t)row * 64 * (int64_t)sizeof(T));
+    }
+    __device__ __forceinline__ void store(T v, int row, int64_t so) const {
+        if constexpr (BUF)
+            bstore(v, rsrc, (uint32_t)so + (uint32_t)(row * 64 * (int)sizeof(T)), 0u);
+        else
+            *reinterpret_cast<T*>(const_cast<char*>(base) + so + (int64_t)row * 64 * (int64_t)sizeof(T)) = v;
+    }
+};
+
+// Site offset in row 0 for elements of type T in tiles of `tb` bytes.
+template <typename T>
+__device__ __forceinline__ int64_t site_off(int32_t site, int64_t tb) {
+    return (int64_t)(site >> 6) * tb + (int64_t)(site & 63) * (int64_t)sizeof(T);
+}
+
+// v_dot2_f32_f16 with a zero accumulator as an inline constant: the
+// compiler otherwise materialises the zero with a move to use the
+// accumulating two-operand form.
+__device__ __forceinline__ float dot2_zero(half2_t a, half2_t b) {
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Neighbour indices of a checkerboard site in the three spatial directions.
 struct SpatialNeighbours {
     int32_t fwd[3];

@@ -163,19 +163,19 @@ __device__ __forceinline__ int32_t displaced_site(const Geometry& g, const int32
 }
 
 template <typename R>
-__device__ __forceinline__ cplx_t<R> load_comp(const char* base, int32_t prec, int64_t plane, int32_t nrec,
-                                               int32_t ncomp, int32_t rec, int32_t k, int32_t site) {
+__device__ __forceinline__ cplx_t<R> load_comp(const char* base, int32_t prec, int32_t nrec, int32_t ncomp,
+                                               int32_t rec, int32_t k, int32_t site) {
     using T2 = cplx_t<R>;
-    const int64_t off = plane_offset(plane, ncomp, prec, rec, k);
+    const char* p = base + comp_offset(nrec, ncomp, prec, rec, k, site);
     if (prec == QDP_F64) {
-        const double2 v = reinterpret_cast<const double2*>(base + off)[site];
+        const double2 v = *reinterpret_cast<const double2*>(p);
         return T2{(R)v.x, (R)v.y};
     } else if (prec == QDP_F32) {
-        const float2 v = reinterpret_cast<const float2*>(base + off)[site];
+        const float2 v = *reinterpret_cast<const float2*>(p);
         return T2{(R)v.x, (R)v.y};
     } else {
-        const half2_t h = reinterpret_cast<const half2_t*>(base + off)[site];
-        const float sc = reinterpret_cast<const float*>(base + scale_offset(plane, nrec, ncomp, rec))[site];
+        const half2_t h = *reinterpret_cast<const half2_t*>(p);
+        const float sc = *reinterpret_cast<const float*>(base + scale_offset(nrec, ncomp, rec, site));
         return T2{(R)((float)h.x * sc), (R)((float)h.y * sc)};
     }
 }
@@ -191,7 +191,7 @@ __device__ __forceinline__ void load_operand(const Operand& op, const Geometry& 
     }
     const int32_t site = op.has_disp ? displaced_site(g, c, op.d) : s;
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = load_comp<R>(op.base, op.prec, g.plane, op.nrec, op.ncomp, op.rec, k, site);
+    for (int k = 0; k < N; ++k) v[k] = load_comp<R>(op.base, op.prec, op.nrec, op.ncomp, op.rec, k, site);
 }
 
 template <typename R>
@@ -200,12 +200,12 @@ __device__ __forceinline__ void store_values(const OutDesc& out, const Geometry&
     if (out.prec == QDP_F64) {
         for (int k = 0; k < N; ++k) {
             double2 w = make_double2((double)v[k].x, out.real_only ? 0.0 : (double)v[k].y);
-            reinterpret_cast<double2*>(out.base + plane_offset(g.plane, out.ncomp, out.prec, 0, k))[s] = w;
+            *reinterpret_cast<double2*>(out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, k, s)) = w;
         }
     } else if (out.prec == QDP_F32) {
         for (int k = 0; k < N; ++k) {
             float2 w = make_float2((float)v[k].x, out.real_only ? 0.f : (float)v[k].y);
-            reinterpret_cast<float2*>(out.base + plane_offset(g.plane, out.ncomp, out.prec, 0, k))[s] = w;
+            *reinterpret_cast<float2*>(out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, k, s)) = w;
         }
     } else {
         float m = 0.f;
@@ -215,9 +215,9 @@ __device__ __forceinline__ void store_values(const OutDesc& out, const Geometry&
         }
         const int e = f16s_exponent(m);
         for (int k = 0; k < N; ++k)
-            reinterpret_cast<half2_t*>(out.base + plane_offset(g.plane, out.ncomp, out.prec, 0, k))[s] =
+            *reinterpret_cast<half2_t*>(out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, k, s)) =
                 f16s_encode((float)v[k].x, out.real_only ? 0.f : (float)v[k].y, e);
-        reinterpret_cast<float*>(out.base + scale_offset(g.plane, out.nrec, out.ncomp, 0))[s] =
+        *reinterpret_cast<float*>(out.base + scale_offset(out.nrec, out.ncomp, 0, s)) =
             m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
     }
 }
@@ -470,14 +470,14 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs A) {
         const int32_t vs = T.vec.has_disp ? displaced_site(A.g, c, T.vec.d) : s;
 #pragma unroll
         for (int k = 0; k < NV; ++k)
-            v[k] = load_comp<R>(T.vec.base, T.vec.prec, A.g.plane, T.vec.nrec, T.vec.ncomp, T.vec.rec, k, vs);
+            v[k] = load_comp<R>(T.vec.base, T.vec.prec, T.vec.nrec, T.vec.ncomp, T.vec.rec, k, vs);
         T2 w[NV];
         if (T.has_mat) {
             T2 m[9];
             const int32_t ms = T.mat.has_disp ? displaced_site(A.g, c, T.mat.d) : s;
 #pragma unroll
             for (int k = 0; k < 9; ++k)
-                m[k] = load_comp<R>(T.mat.base, T.mat.prec, A.g.plane, T.mat.nrec, T.mat.ncomp, T.mat.rec, k, ms);
+                m[k] = load_comp<R>(T.mat.base, T.mat.prec, T.mat.nrec, T.mat.ncomp, T.mat.rec, k, ms);
 #pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp)
 #pragma unroll
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs A) {
     double re = 0.0, im = 0.0;
     for (int64_t l = (int64_t)chunk * blockDim.x + threadIdx.x; l < d.count; l += (int64_t)A.nchunks * blockDim.x) {
         const int32_t s = (int32_t)subset_site(A.g, d, l);
-        const double2 v = load_comp<double>(A.base, A.prec, A.g.plane, A.nrec, A.ncomp, 0, k, s);
+        const double2 v = load_comp<double>(A.base, A.prec, A.nrec, A.ncomp, 0, k, s);
         re += v.x;
         im += v.y;
     }

@@ -74,8 +74,8 @@ struct Ctx {
 
     // smearing: launch-shape tuning and graph cache
     std::map<SmearTuneKey, qdp_launch_shape> tuned;
-    qdp_launch_shape forced{0, 0, 0, 0};
-    qdp_launch_shape last_shape{0, 0, 0, 0};
+    qdp_launch_shape forced{0, 0, 0, 0, 0, 0};
+    qdp_launch_shape last_shape{0, 0, 0, 0, 0, 0};
     std::map<std::string, GraphEntry> graphs;
     uint64_t graph_tick = 0;
 

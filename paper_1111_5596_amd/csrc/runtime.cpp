@@ -216,13 +216,13 @@ void to_device_layout(const Geometry& g, int32_t type, int32_t prec, const doubl
                             const size_t hi = host_index(g, type, s, r, k);
                             const double re = host[hi];
                             const double im = type == QDP_REAL ? 0.0 : host[hi + 1];
-                            char* p = base + plane_offset(g.plane, sh.ncomp, prec, r, k);
+                            char* p = base + comp_offset(sh.nrec, sh.ncomp, prec, r, k, c);
                             if (prec == QDP_F64) {
-                                double* d = reinterpret_cast<double*>(p) + 2 * c;
+                                double* d = reinterpret_cast<double*>(p);
                                 d[0] = re;
                                 d[1] = im;
                             } else if (prec == QDP_F32) {
-                                float* d = reinterpret_cast<float*>(p) + 2 * c;
+                                float* d = reinterpret_cast<float*>(p);
                                 d[0] = (float)re;
                                 d[1] = (float)im;
                             } else {
@@ -235,12 +235,11 @@ void to_device_layout(const Geometry& g, int32_t type, int32_t prec, const doubl
                             encode_f16s(rec.data(), sh.ncomp, q.data(), &sc);
                             for (int32_t k = 0; k < sh.ncomp; ++k) {
                                 _Float16* d = reinterpret_cast<_Float16*>(
-                                                  base + plane_offset(g.plane, sh.ncomp, prec, r, k)) +
-                                              2 * c;
+                                    base + comp_offset(sh.nrec, sh.ncomp, prec, r, k, c));
                                 d[0] = q[2 * k];
                                 d[1] = q[2 * k + 1];
                             }
-                            reinterpret_cast<float*>(base + scale_offset(g.plane, sh.nrec, sh.ncomp, r))[c] = sc;
+                            *reinterpret_cast<float*>(base + scale_offset(sh.nrec, sh.ncomp, r, c)) = sc;
                         }
                     }
                 }
@@ -258,19 +257,19 @@ void from_device_layout(const Geometry& g, int32_t type, int32_t prec, const cha
                     for (int32_t r = 0; r < sh.nrec; ++r) {
                         float sc = 1.f;
                         if (prec == QDP_F16S)
-                            sc = reinterpret_cast<const float*>(base + scale_offset(g.plane, sh.nrec, sh.ncomp, r))[c];
+                            sc = *reinterpret_cast<const float*>(base + scale_offset(sh.nrec, sh.ncomp, r, c));
                         for (int32_t k = 0; k < sh.ncomp; ++k) {
-                            const char* p = base + plane_offset(g.plane, sh.ncomp, prec, r, k);
+                            const char* p = base + comp_offset(sh.nrec, sh.ncomp, prec, r, k, c);
                             double re, im;
                             if (prec == QDP_F64) {
-                                re = reinterpret_cast<const double*>(p)[2 * c];
-                                im = reinterpret_cast<const double*>(p)[2 * c + 1];
+                                re = reinterpret_cast<const double*>(p)[0];
+                                im = reinterpret_cast<const double*>(p)[1];
                             } else if (prec == QDP_F32) {
-                                re = reinterpret_cast<const float*>(p)[2 * c];
-                                im = reinterpret_cast<const float*>(p)[2 * c + 1];
+                                re = reinterpret_cast<const float*>(p)[0];
+                                im = reinterpret_cast<const float*>(p)[1];
                             } else {
-                                re = (double)((float)reinterpret_cast<const _Float16*>(p)[2 * c] * sc);
-                                im = (double)((float)reinterpret_cast<const _Float16*>(p)[2 * c + 1] * sc);
+                                re = (double)((float)reinterpret_cast<const _Float16*>(p)[0] * sc);
+                                im = (double)((float)reinterpret_cast<const _Float16*>(p)[1] * sc);
                             }
                             const size_t hi = host_index(g, type, s, r, k);
                             host[hi] = re;
@@ -521,7 +520,8 @@ qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape) {
     if (shape->site_waves != 0) {
         const int sw = shape->site_waves, cg = shape->col_groups;
         if (sw < 1 || cg < 1 || cg > 12 || sw * cg > 4 || shape->xcd < 0 || shape->xcd > 1 ||
-            !(shape->waves_per_simd == 0 || shape->waves_per_simd == 2 || shape->waves_per_simd == 3))
+            !(shape->waves_per_simd == 0 || shape->waves_per_simd == 2 || shape->waves_per_simd == 3) ||
+            shape->flat < 0 || shape->flat > 1)
             return set_error(ctx, QDP_ERR_ARG, "launch shape out of range (site_waves * col_groups <= 4)");
     }
     ctx->forced = *shape;

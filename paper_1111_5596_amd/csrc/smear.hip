@@ -20,6 +20,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -50,28 +52,46 @@ struct SmearLaunch {
 };
 
 // ---------------------------------------------------------------------------
+// Memory access of the per-site updates.  BUF = true: raw buffer loads with
+// one byte offset per neighbour site shared by every component row (needs
+// every field below 4 GiB); BUF = false: flat 64-bit addresses.  Both feed
+// the same arithmetic, so they produce identical bits.
+// ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
 // Per-site update, FP64 / FP32 storage (arithmetic in the storage type)
 // ---------------------------------------------------------------------------
 
-template <typename R>
+template <typename R, bool BUF>
 __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s, int c0, int c1,
                                                  R kappa) {
     using T2 = cplx_t<R>;
-    const int64_t plane = job.g.plane;
     const SpatialNeighbours nb = spatial_neighbours(job.g, s);
-    const T2* __restrict__ U = reinterpret_cast<const T2*>(job.gauge);
+    constexpr int PREC = sizeof(R) == 8 ? QDP_F64 : QDP_F32;
+    const int64_t tbu = tile_bytes(4, 9, PREC), tbc = tile_bytes(1, 12, PREC);
+    const FieldRef<T2, BUF> U(job.gauge);
+    // site offsets: links at x and x - i, column values at x, x + i, x - i
+    const int64_t us = site_off<T2>(s, tbu);
+    const int64_t cs = site_off<T2>(s, tbc);
+    int64_t ub_off[3], cf[3], cb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ub_off[i] = site_off<T2>(nb.bwd[i], tbu);
+        cf[i] = site_off<T2>(nb.fwd[i], tbc);
+        cb[i] = site_off<T2>(nb.bwd[i], tbc);
+    }
 
     T2 uf[3][9], ub[3][9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            uf[i][k] = U[(int64_t)(i * 9 + k) * plane + s];
-            ub[i][k] = U[(int64_t)(i * 9 + k) * plane + nb.bwd[i]];
+            uf[i][k] = U.load(i * 9 + k, us);
+            ub[i][k] = U.load(i * 9 + k, ub_off[i]);
         }
 
     for (int c = c0; c < c1; ++c) {
-        const T2* __restrict__ src = reinterpret_cast<const T2*>(job.src[c]);
+        const FieldRef<T2, BUF> src(job.src[c]);
         T2 acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = T2{0, 0};
@@ -80,7 +100,7 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
             {
                 T2 v[12];
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.fwd[i]];
+                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cf[i]);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -91,7 +111,7 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
             {
                 T2 v[12];
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.bwd[i]];
+                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cb[i]);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -101,13 +121,13 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
                             cmac_conj(acc[3 * sp + a], ub[i][3 * b + a], v[3 * sp + b]);
             }
         }
-        T2* __restrict__ dst = reinterpret_cast<T2*>(job.dst[c]);
+        const FieldRef<T2, BUF> dst(job.dst[c]);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            T2 o = src[(int64_t)k * plane + s];
+            T2 o = src.load(k, cs);
             o.x = fmadd(kappa, acc[k].x, o.x);
             o.y = fmadd(kappa, acc[k].y, o.y);
-            dst[(int64_t)k * plane + s] = o;
+            dst.store(o, k, cs);
         }
     }
 }
@@ -120,13 +140,24 @@ __device__ __forceinline__ float dot2(half2_t a, half2_t b, float c) {
     return __builtin_amdgcn_fdot2(a, b, c, false);
 }
 
+template <bool BUF>
 __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s, int c0, int c1,
                                                  float kappa) {
-    const int64_t plane = job.g.plane;
+    // half2 rows and FP32 scale rows have the same 4-byte elements, so the
+    // scale row of gauge record i is row 36 + i, of a column row 12
     const SpatialNeighbours nb = spatial_neighbours(job.g, s);
-    const half2_t* __restrict__ U = reinterpret_cast<const half2_t*>(job.gauge);
-    const float* __restrict__ Us =
-        reinterpret_cast<const float*>(job.gauge + scale_offset(plane, 4, 9, 0));
+    const int64_t tbu = tile_bytes(4, 9, QDP_F16S), tbc = tile_bytes(1, 12, QDP_F16S);
+    const FieldRef<half2_t, BUF> U(job.gauge);
+    const FieldRef<float, BUF> Us(job.gauge);
+    const int64_t us = site_off<half2_t>(s, tbu);
+    const int64_t cs = site_off<half2_t>(s, tbc);
+    int64_t ub_off[3], cf[3], cb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ub_off[i] = site_off<half2_t>(nb.bwd[i], tbu);
+        cf[i] = site_off<half2_t>(nb.fwd[i], tbc);
+        cb[i] = site_off<half2_t>(nb.bwd[i], tbc);
+    }
 
     // forward link u: re(u v) = (u.x, -u.y).v   im(u v) = (u.y, u.x).v
     // backward link w: re(w* v) = (w.x, w.y).v  im(w* v) = (-w.y, w.x).v
@@ -134,12 +165,12 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
     float sf[3], sb[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        sf[i] = Us[(int64_t)i * plane + s];
-        sb[i] = Us[(int64_t)i * plane + nb.bwd[i]];
+        sf[i] = Us.load(36 + i, us);
+        sb[i] = Us.load(36 + i, ub_off[i]);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const half2_t u = U[(int64_t)(i * 9 + k) * plane + s];
-            const half2_t w = U[(int64_t)(i * 9 + k) * plane + nb.bwd[i]];
+            const half2_t u = U.load(i * 9 + k, us);
+            const half2_t w = U.load(i * 9 + k, ub_off[i]);
             fre[i][k] = half2_t{u.x, (_Float16)(-u.y)};
             fim[i][k] = half2_t{u.y, u.x};
             bre[i][k] = w;
@@ -148,9 +179,8 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
     }
 
     for (int c = c0; c < c1; ++c) {
-        const half2_t* __restrict__ src = reinterpret_cast<const half2_t*>(job.src[c]);
-        const float* __restrict__ ssc =
-            reinterpret_cast<const float*>(job.src[c] + scale_offset(plane, 1, 12, 0));
+        const FieldRef<half2_t, BUF> src(job.src[c]);
+        const FieldRef<float, BUF> ssc(job.src[c]);
         float2 acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
@@ -159,15 +189,16 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
             {
                 half2_t v[12];
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.fwd[i]];
-                const float sc = sf[i] * ssc[nb.fwd[i]];
+                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cf[i]);
+                const float sc = sf[i] * ssc.load(12, cf[i]);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        float tre = 0.f, tim = 0.f;
+                        float tre = dot2_zero(fre[i][3 * a], v[3 * sp]);
+                        float tim = dot2_zero(fim[i][3 * a], v[3 * sp]);
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) {
+                        for (int b = 1; b < 3; ++b) {
                             tre = dot2(fre[i][3 * a + b], v[3 * sp + b], tre);
                             tim = dot2(fim[i][3 * a + b], v[3 * sp + b], tim);
                         }
@@ -178,15 +209,16 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
             {
                 half2_t v[12];
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src[(int64_t)k * plane + nb.bwd[i]];
-                const float sc = sb[i] * ssc[nb.bwd[i]];
+                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cb[i]);
+                const float sc = sb[i] * ssc.load(12, cb[i]);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        float tre = 0.f, tim = 0.f;
+                        float tre = dot2_zero(bre[i][a], v[3 * sp]);
+                        float tim = dot2_zero(bim[i][a], v[3 * sp]);
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) {
+                        for (int b = 1; b < 3; ++b) {
                             tre = dot2(bre[i][3 * b + a], v[3 * sp + b], tre);
                             tim = dot2(bim[i][3 * b + a], v[3 * sp + b], tim);
                         }
@@ -196,43 +228,45 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
             }
         }
         // psi + kappa * acc, then requantise the record
-        const float so = ssc[s];
+        const float so = ssc.load(12, cs);
         float2 out[12];
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const float2 o = f16s_decode(src[(int64_t)k * plane + s], so);
+            const float2 o = f16s_decode(src.load(k, cs), so);
             out[k].x = fmadd(kappa, acc[k].x, o.x);
             out[k].y = fmadd(kappa, acc[k].y, o.y);
             m = fmaxf(m, fmaxf(fabsf(out[k].x), fabsf(out[k].y)));
         }
         const int e = f16s_exponent(m);
-        half2_t* __restrict__ dst = reinterpret_cast<half2_t*>(job.dst[c]);
-        float* __restrict__ dsc = reinterpret_cast<float*>(job.dst[c] + scale_offset(plane, 1, 12, 0));
+        const FieldRef<half2_t, BUF> dst(job.dst[c]);
+        const FieldRef<float, BUF> dsc(job.dst[c]);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) dst[(int64_t)k * plane + s] = f16s_encode(out[k].x, out[k].y, e);
-        dsc[s] = m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
+        for (int k = 0; k < 12; ++k) dst.store(f16s_encode(out[k].x, out[k].y, e), k, cs);
+        dsc.store(m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f, 12, cs);
     }
 }
 
-template <int PREC>
+template <int PREC, bool BUF>
 __device__ __forceinline__ void site_update(const SmearJob& job, int32_t s, int c0, int c1,
                                             double kappa) {
     if constexpr (PREC == QDP_F64) {
-        site_update_real<double>(job, s, c0, c1, kappa);
+        site_update_real<double, BUF>(job, s, c0, c1, kappa);
     } else if constexpr (PREC == QDP_F32) {
-        site_update_real<float>(job, s, c0, c1, (float)kappa);
+        site_update_real<float, BUF>(job, s, c0, c1, (float)kappa);
     } else {
-        site_update_f16s(job, s, c0, c1, (float)kappa);
+        site_update_f16s<BUF>(job, s, c0, c1, (float)kappa);
     }
 }
 
 // Thread -> (site, column group) inside a tile of 64 * site_waves sites.
-template <int PREC>
+template <int PREC, bool BUF>
 __device__ __forceinline__ void tile_update(const SmearJob& job, int64_t tile, int64_t site_begin,
                                            int64_t site_count, int site_waves, int col_groups,
                                            double kappa) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform across the wavefront: keep it (and the
+    // column range it selects) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int group = wave % col_groups, sw = wave / col_groups;
     const int64_t local = (tile * site_waves + sw) * 64 + lane;
     if (local >= site_count) return;
@@ -240,25 +274,25 @@ __device__ __forceinline__ void tile_update(const SmearJob& job, int64_t tile, i
     const int c0 = group * cpt;
     const int c1 = min(job.ncols, c0 + cpt);
     if (c0 >= c1) return;
-    site_update<PREC>(job, (int32_t)(site_begin + local), c0, c1, kappa);
+    site_update<PREC, BUF>(job, (int32_t)(site_begin + local), c0, c1, kappa);
 }
 
 // OCC is the occupancy target handed to the register allocator (waves per
 // SIMD; 0 = the compiler's choice).  More waves hide more memory latency but
 // leave fewer registers for the six links and the prefetched neighbours.
-template <int PREC, int OCC>
+template <int PREC, int OCC, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_kernel(
     SmearJob job, SmearLaunch ln) {
     int64_t b = blockIdx.x;
     if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
     if (b >= ln.nlogical) return;
-    tile_update<PREC>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.kappa);
+    tile_update<PREC, BUF>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.kappa);
 }
 
 // Persistent multi-lattice kernel: a fixed grid walks a work list of
 // (lattice, tile) items; block b takes a contiguous run of items (XCD-aware
 // so one XCD's blocks share neighbouring tiles).
-template <int PREC, int OCC>
+template <int PREC, int OCC, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_batch_kernel(
     const SmearJob* __restrict__ jobs,
                                                           const int64_t* __restrict__ tile_start,
@@ -281,7 +315,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
             j = lo;
         }
         const SmearJob& job = jobs[j];
-        tile_update<PREC>(job, t - tile_start[j], 0, job.g.V, ln.site_waves, ln.col_groups,
+        tile_update<PREC, BUF>(job, t - tile_start[j], 0, job.g.V, ln.site_waves, ln.col_groups,
                           ln.kappa);
     }
 }
@@ -375,44 +409,36 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
     return QDP_OK;
 }
 
-// Occupancy variants compiled per precision (FP64 keeps the compiler's
-// choice: its links alone need 216 registers).
-template <int PREC>
-void* smear_func_occ(int occ) {
+// Kernel variants: occupancy target (FP64 keeps the compiler's choice: its
+// links alone need 216 registers) x addressing (buffer / flat).
+template <int PREC, bool BUF>
+void* smear_func_occ(int occ, bool batch) {
     if constexpr (PREC == QDP_F64) {
-        return reinterpret_cast<void*>(&smear_kernel<PREC, 0>);
+        return batch ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 0, BUF>)
+                     : reinterpret_cast<void*>(&smear_kernel<PREC, 0, BUF>);
     } else {
-        return occ == 3 ? reinterpret_cast<void*>(&smear_kernel<PREC, 3>)
-             : occ == 2 ? reinterpret_cast<void*>(&smear_kernel<PREC, 2>)
-                        : reinterpret_cast<void*>(&smear_kernel<PREC, 0>);
+        if (batch)
+            return occ == 3 ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 3, BUF>)
+                 : occ == 2 ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 2, BUF>)
+                            : reinterpret_cast<void*>(&smear_batch_kernel<PREC, 0, BUF>);
+        return occ == 3 ? reinterpret_cast<void*>(&smear_kernel<PREC, 3, BUF>)
+             : occ == 2 ? reinterpret_cast<void*>(&smear_kernel<PREC, 2, BUF>)
+                        : reinterpret_cast<void*>(&smear_kernel<PREC, 0, BUF>);
     }
 }
 
-template <int PREC>
-void* smear_batch_func_occ(int occ) {
-    if constexpr (PREC == QDP_F64) {
-        return reinterpret_cast<void*>(&smear_batch_kernel<PREC, 0>);
-    } else {
-        return occ == 3 ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 3>)
-             : occ == 2 ? reinterpret_cast<void*>(&smear_batch_kernel<PREC, 2>)
-                        : reinterpret_cast<void*>(&smear_batch_kernel<PREC, 0>);
-    }
-}
-
-void* smear_func(int prec, int occ) {
+template <bool BUF>
+void* smear_func_buf(int prec, int occ, bool batch) {
     switch (prec) {
-        case QDP_F64: return smear_func_occ<QDP_F64>(occ);
-        case QDP_F32: return smear_func_occ<QDP_F32>(occ);
-        default: return smear_func_occ<QDP_F16S>(occ);
+        case QDP_F64: return smear_func_occ<QDP_F64, BUF>(occ, batch);
+        case QDP_F32: return smear_func_occ<QDP_F32, BUF>(occ, batch);
+        default: return smear_func_occ<QDP_F16S, BUF>(occ, batch);
     }
 }
 
-void* smear_batch_func(int prec, int occ) {
-    switch (prec) {
-        case QDP_F64: return smear_batch_func_occ<QDP_F64>(occ);
-        case QDP_F32: return smear_batch_func_occ<QDP_F32>(occ);
-        default: return smear_batch_func_occ<QDP_F16S>(occ);
-    }
+void* smear_func(int prec, const qdp_launch_shape& sh, bool batch) {
+    return sh.flat ? smear_func_buf<false>(prec, sh.waves_per_simd, batch)
+                   : smear_func_buf<true>(prec, sh.waves_per_simd, batch);
 }
 
 Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t count,
@@ -429,14 +455,14 @@ Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t 
     int64_t grid = ln.nlogical;
     if (sh.xcd) grid = (grid + 7) / 8 * 8;
     Launch L;
-    L.func = smear_func(prec, sh.waves_per_simd);
+    L.func = smear_func(prec, sh, false);
     L.grid = dim3((unsigned)grid);
     L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
     pack_args(L, job, ln);
     return L;
 }
 
-qdp_launch_shape default_shape() { return qdp_launch_shape{4, 1, 1, 2}; }
+qdp_launch_shape default_shape() { return qdp_launch_shape{4, 1, 1, 2, 0, 0}; }
 
 // Validate a list of columns against the gauge field; returns precision and
 // lattice through the out arguments.
@@ -466,6 +492,14 @@ qdp_status check_aliasing(Ctx* ctx, const uint64_t* src, const uint64_t* dst, in
                 return set_error(ctx, QDP_ERR_ALIAS, "smear: destination column %d aliases column %d", a, b);
         }
     return QDP_OK;
+}
+
+// Buffer addressing needs every byte offset of the links and of a column
+// below 4 GiB.
+bool needs_flat(Ctx* ctx, uint64_t gauge, uint64_t lattice, int32_t prec) {
+    const Geometry& g = find_lattice(ctx, lattice)->geo;
+    const int64_t limit = (int64_t(1) << 32) - 1;
+    return find_field(ctx, gauge)->bytes > limit || field_bytes(g, QDP_FERMION, prec) > limit;
 }
 
 // Time one launch shape on the first pass (it writes only the buffer the
@@ -499,9 +533,10 @@ qdp_status time_shape(Ctx* ctx, int prec, const SmearJob& job, int64_t begin, in
 }
 
 qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const SmearJob& job,
-                        int64_t begin, int64_t count, double kappa, qdp_launch_shape* out) {
+                        int64_t begin, int64_t count, double kappa, int flat, qdp_launch_shape* out) {
     if (ctx->forced.site_waves > 0) {
         *out = ctx->forced;
+        out->flat = out->flat | flat;
         return QDP_OK;
     }
     auto it = ctx->tuned.find(key);
@@ -510,6 +545,8 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
         return QDP_OK;
     }
     qdp_launch_shape best = default_shape();
+    best.flat = flat;
+    const bool log = std::getenv("QDP_AUTOTUNE_LOG") != nullptr;
     const int64_t work = count * job.ncols;
     if (!(ctx->flags & QDP_INIT_NO_AUTOTUNE) && work >= (1 << 20)) {
         float best_ms = 1e30f;
@@ -520,9 +557,12 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
                 for (int xcd : {0, 1})
                     for (int occ : {0, 2, 3}) {
                     if (prec == QDP_F64 && occ) continue;
-                    qdp_launch_shape sh{sw, cg, xcd, occ};
+                    qdp_launch_shape sh{sw, cg, xcd, occ, flat, 0};
                     float ms;
                     QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));
+                    if (log)
+                        std::fprintf(stderr, "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d: %.4f ms\n",
+                                     prec, job.ncols, (long long)count, sw, cg, xcd, occ, flat, ms);
                     if (ms < best_ms) {
                         best_ms = ms;
                         best = sh;
@@ -622,7 +662,8 @@ qdp_status smear_jacobi_impl(Ctx* ctx, uint64_t gauge, const uint64_t* src, cons
 
         SmearTuneKey key{{g.L[0], g.L[1], g.L[2], g.L[3]}, ncols, prec, mode, 0};
         qdp_launch_shape sh;
-        QDP_CHECK(choose_shape(ctx, key, prec, first, passes[0].begin, passes[0].count, kappa, &sh));
+        const int flat = needs_flat(ctx, gauge, lat, prec) ? 1 : 0;
+        QDP_CHECK(choose_shape(ctx, key, prec, first, passes[0].begin, passes[0].count, kappa, flat, &sh));
         ctx->last_shape = sh;
 
         std::vector<Launch> ls;
@@ -692,6 +733,8 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
     }
 
     qdp_launch_shape sh = ctx->forced.site_waves > 0 ? ctx->forced : default_shape();
+    for (int32_t j = 0; j < njobs; ++j)
+        if (needs_flat(ctx, jobs[j].gauge, lats[j], prec)) sh.flat = 1;
     ctx->last_shape = sh;
     const int64_t tile_sites = 64LL * sh.site_waves;
 
@@ -750,7 +793,7 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
         const SmearJob* J = reinterpret_cast<const SmearJob*>(k == 1 ? d_first : (k % 2 == 0 ? d_dst : d_tmp));
         const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles);
         Launch L;
-        L.func = smear_batch_func(prec, sh.waves_per_simd);
+        L.func = smear_func(prec, sh, true);
         L.grid = dim3((unsigned)grid);
         L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
         pack_args(L, J, T, njobs, ln);

@@ -52,24 +52,22 @@ __device__ __forceinline__ double2 complex_normal(uint64_t seed, uint32_t stream
 }
 
 // Store one record of n complex doubles at checkerboard site s.
-__device__ void store_record(char* base, int32_t prec, int64_t plane, int32_t nrec, int32_t ncomp, int32_t rec,
-                             int32_t s, const double2* v, int n) {
+__device__ void store_record(char* base, int32_t prec, int32_t nrec, int32_t ncomp, int32_t rec, int32_t s,
+                             const double2* v, int n) {
     if (prec == QDP_F64) {
-        for (int k = 0; k < n; ++k)
-            reinterpret_cast<double2*>(base + plane_offset(plane, ncomp, prec, rec, k))[s] = v[k];
+        for (int k = 0; k < n; ++k) *reinterpret_cast<double2*>(base + comp_offset(nrec, ncomp, prec, rec, k, s)) = v[k];
     } else if (prec == QDP_F32) {
         for (int k = 0; k < n; ++k)
-            reinterpret_cast<float2*>(base + plane_offset(plane, ncomp, prec, rec, k))[s] =
+            *reinterpret_cast<float2*>(base + comp_offset(nrec, ncomp, prec, rec, k, s)) =
                 make_float2((float)v[k].x, (float)v[k].y);
     } else {
         float m = 0.f;
         for (int k = 0; k < n; ++k) m = fmaxf(m, fmaxf(fabsf((float)v[k].x), fabsf((float)v[k].y)));
         const int e = f16s_exponent(m);
         for (int k = 0; k < n; ++k)
-            reinterpret_cast<half2_t*>(base + plane_offset(plane, ncomp, prec, rec, k))[s] =
+            *reinterpret_cast<half2_t*>(base + comp_offset(nrec, ncomp, prec, rec, k, s)) =
                 f16s_encode((float)v[k].x, (float)v[k].y, e);
-        reinterpret_cast<float*>(base + scale_offset(plane, nrec, ncomp, rec))[s] =
-            m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
+        *reinterpret_cast<float*>(base + scale_offset(nrec, ncomp, rec, s)) = m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
     }
 }
 
@@ -125,7 +123,7 @@ __global__ __launch_bounds__(256) void su3_kernel(Geometry g, char* base, int32_
         r /= g.L[d];
     }
     const int32_t cb = (int32_t)cb_index(g, c[0], c[1], c[2], c[3]);
-    store_record(base, prec, g.plane, 4, 9, mu, cb, out, 9);
+    store_record(base, prec, 4, 9, mu, cb, out, 9);
 }
 
 __global__ __launch_bounds__(256) void gaussian_kernel(Geometry g, char* base, int32_t prec, uint64_t seed,
@@ -143,7 +141,7 @@ __global__ __launch_bounds__(256) void gaussian_kernel(Geometry g, char* base, i
         c[d] = (int32_t)(r % g.L[d]);
         r /= g.L[d];
     }
-    store_record(base, prec, g.plane, 1, 12, 0, (int32_t)cb_index(g, c[0], c[1], c[2], c[3]), v, 12);
+    store_record(base, prec, 1, 12, 0, (int32_t)cb_index(g, c[0], c[1], c[2], c[3]), v, 12);
 }
 
 // Zero a FERMION field (F16S scales set to 1), then put 1 at one component.
@@ -153,7 +151,7 @@ __global__ __launch_bounds__(256) void point_kernel(Geometry g, char* base, int3
     if (s >= g.V) return;
     double2 v[12];
     for (int k = 0; k < 12; ++k) v[k] = make_double2(s == target && k == comp ? 1.0 : 0.0, 0.0);
-    store_record(base, prec, g.plane, 1, 12, 0, (int32_t)s, v, 12);
+    store_record(base, prec, 1, 12, 0, (int32_t)s, v, 12);
 }
 
 }  // namespace

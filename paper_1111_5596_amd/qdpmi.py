@@ -81,7 +81,8 @@ class qdp_cache_stats_t(ctypes.Structure):
 
 class qdp_launch_shape(ctypes.Structure):
     _fields_ = [("site_waves", ctypes.c_int32), ("col_groups", ctypes.c_int32),
-                ("xcd", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+                ("xcd", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("flat", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _c = ctypes
@@ -343,14 +344,14 @@ class Context:
     def fault_alloc_after(self, n):
         self.check(lib.qdp_fault_alloc_after(self.h, n))
 
-    def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0):
-        s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd)
+    def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0):
+        s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, 0)
         self.check(lib.qdp_smear_set_shape(self.h, ctypes.byref(s)))
 
     def get_shape(self):
         s = qdp_launch_shape()
         self.check(lib.qdp_smear_get_shape(self.h, ctypes.byref(s)))
-        return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd)
+        return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd, s.flat)
 
     def sync(self):
         self.check(lib.qdp_sync(self.h))

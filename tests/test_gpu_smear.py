@@ -108,7 +108,7 @@ def test_even_odd_equals_full_bitwise(qdp, prec):
     free_all(qdp, [g] + a + b)
 
 
-@pytest.mark.parametrize("prec", ["F32", "F16S"])
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16S"])
 def test_launch_shapes_bitwise(qdp, prec):
     dims = (8, 8, 4, 4)
     U = synth.su3_links(dims, 4)
@@ -117,12 +117,12 @@ def test_launch_shapes_bitwise(qdp, prec):
     out = qdp.alloc(lat, "FERMION", prec)
     ref = None
     try:
-        for sw, cg, xcd, occ in [(1, 1, 0, 0), (4, 1, 1, 2), (2, 2, 1, 3), (1, 3, 0, 2), (1, 4, 1, 0),
-                                 (2, 1, 0, 3)]:
-            qdp.set_shape(sw, cg, xcd, occ)
+        for sw, cg, xcd, occ, flat in [(1, 1, 0, 0, 0), (4, 1, 1, 2, 0), (2, 2, 1, 3, 0), (1, 3, 0, 2, 1),
+                                       (1, 4, 1, 0, 1), (2, 1, 0, 3, 1), (4, 1, 1, 2, 1)]:
+            qdp.set_shape(sw, cg, xcd, occ, flat)
             outs = [qdp.alloc(lat, "FERMION", prec) for _ in fs]
             qdp.smear_to(g, fs, outs, 0.25, 5, mode=1)
-            assert qdp.get_shape() == (sw, cg, xcd, occ)
+            assert qdp.get_shape() == (sw, cg, xcd, occ, flat)
             vals = [qdp.read(o) for o in outs]
             if ref is None:
                 ref = vals
