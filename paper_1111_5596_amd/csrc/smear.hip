@@ -95,36 +95,44 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
         T2 acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = T2{0, 0};
+        // Two load batches per column (the three forward neighbours, then the
+        // three backward neighbours and the site itself), each requested in
+        // full before its arithmetic: two waits on memory per column while
+        // the links stay in registers.
+        T2 v[3][12];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            {
-                T2 v[12];
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cf[i]);
+            for (int k = 0; k < 12; ++k) v[i][k] = src.load(k, cf[i]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
+            for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) cmac(acc[3 * sp + a], uf[i][3 * a + b], v[3 * sp + b]);
-            }
-            {
-                T2 v[12];
+                for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cb[i]);
+                    for (int b = 0; b < 3; ++b) cmac(acc[3 * sp + a], uf[i][3 * a + b], v[i][3 * sp + b]);
+        T2 own[12];
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 12; ++k) v[i][k] = src.load(k, cb[i]);
 #pragma unroll
-                        for (int b = 0; b < 3; ++b)
-                            cmac_conj(acc[3 * sp + a], ub[i][3 * b + a], v[3 * sp + b]);
-            }
-        }
+        for (int k = 0; k < 12; ++k) own[k] = src.load(k, cs);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) cmac_conj(acc[3 * sp + a], ub[i][3 * b + a], v[i][3 * sp + b]);
         const FieldRef<T2, BUF> dst(job.dst[c]);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            T2 o = src.load(k, cs);
+            T2 o = own[k];
             o.x = fmadd(kappa, acc[k].x, o.x);
             o.y = fmadd(kappa, acc[k].y, o.y);
             dst.store(o, k, cs);
@@ -181,46 +189,62 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
     for (int c = c0; c < c1; ++c) {
         const FieldRef<half2_t, BUF> src(job.src[c]);
         const FieldRef<float, BUF> ssc(job.src[c]);
+        // Load phase: every neighbour record of this column (6 x 12 half2 and
+        // their scales) and the site's own record are requested before any
+        // arithmetic, so the wavefront waits for memory once per column.
+        half2_t v[6][12], own[12];
+        float vsc[6], so;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                v[2 * i][k] = src.load(k, cf[i]);
+                v[2 * i + 1][k] = src.load(k, cb[i]);
+            }
+            vsc[2 * i] = ssc.load(12, cf[i]);
+            vsc[2 * i + 1] = ssc.load(12, cb[i]);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) own[k] = src.load(k, cs);
+        so = ssc.load(12, cs);
+        __builtin_amdgcn_sched_barrier(0);
+
         float2 acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             {
-                half2_t v[12];
-#pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cf[i]);
-                const float sc = sf[i] * ssc.load(12, cf[i]);
+                const half2_t* vv = v[2 * i];
+                const float sc = sf[i] * vsc[2 * i];
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        float tre = dot2_zero(fre[i][3 * a], v[3 * sp]);
-                        float tim = dot2_zero(fim[i][3 * a], v[3 * sp]);
+                        float tre = dot2_zero(fre[i][3 * a], vv[3 * sp]);
+                        float tim = dot2_zero(fim[i][3 * a], vv[3 * sp]);
 #pragma unroll
                         for (int b = 1; b < 3; ++b) {
-                            tre = dot2(fre[i][3 * a + b], v[3 * sp + b], tre);
-                            tim = dot2(fim[i][3 * a + b], v[3 * sp + b], tim);
+                            tre = dot2(fre[i][3 * a + b], vv[3 * sp + b], tre);
+                            tim = dot2(fim[i][3 * a + b], vv[3 * sp + b], tim);
                         }
                         acc[3 * sp + a].x = fmadd(sc, tre, acc[3 * sp + a].x);
                         acc[3 * sp + a].y = fmadd(sc, tim, acc[3 * sp + a].y);
                     }
             }
             {
-                half2_t v[12];
-#pragma unroll
-                for (int k = 0; k < 12; ++k) v[k] = src.load(k, cb[i]);
-                const float sc = sb[i] * ssc.load(12, cb[i]);
+                const half2_t* vv = v[2 * i + 1];
+                const float sc = sb[i] * vsc[2 * i + 1];
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        float tre = dot2_zero(bre[i][a], v[3 * sp]);
-                        float tim = dot2_zero(bim[i][a], v[3 * sp]);
+                        float tre = dot2_zero(bre[i][a], vv[3 * sp]);
+                        float tim = dot2_zero(bim[i][a], vv[3 * sp]);
 #pragma unroll
                         for (int b = 1; b < 3; ++b) {
-                            tre = dot2(bre[i][3 * b + a], v[3 * sp + b], tre);
-                            tim = dot2(bim[i][3 * b + a], v[3 * sp + b], tim);
+                            tre = dot2(bre[i][3 * b + a], vv[3 * sp + b], tre);
+                            tim = dot2(bim[i][3 * b + a], vv[3 * sp + b], tim);
                         }
                         acc[3 * sp + a].x = fmadd(sc, tre, acc[3 * sp + a].x);
                         acc[3 * sp + a].y = fmadd(sc, tim, acc[3 * sp + a].y);
@@ -228,12 +252,11 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
             }
         }
         // psi + kappa * acc, then requantise the record
-        const float so = ssc.load(12, cs);
         float2 out[12];
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const float2 o = f16s_decode(src.load(k, cs), so);
+            const float2 o = f16s_decode(own[k], so);
             out[k].x = fmadd(kappa, acc[k].x, o.x);
             out[k].y = fmadd(kappa, acc[k].y, o.y);
             m = fmaxf(m, fmaxf(fabsf(out[k].x), fabsf(out[k].y)));
