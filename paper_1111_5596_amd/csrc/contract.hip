@@ -42,31 +42,41 @@ struct ContractArgs {
     int32_t pad;
 };
 
-// Load one 12-component column at checkerboard site s; FP32 and F16S values
-// are returned as float2 (F16S decoded with its record scale), FP64 as
-// double2.  Products are formed in FP64 by the caller.
+// One 12-component column at one checkerboard site, as loaded: FP64 and FP32
+// values, or F16S half2 values with the record scale (decoded when used, so
+// an in-flight record takes 13 registers).  Products are formed in FP64.
 template <int PREC>
-using ColT = typename std::conditional<PREC == QDP_F64, double2, float2>::type;
+struct RawCol {
+    typename std::conditional<PREC == QDP_F64, double2, float2>::type v[12];
+    __device__ __forceinline__ double2 at(int k) const { return make_double2(v[k].x, v[k].y); }
+};
+template <>
+struct RawCol<QDP_F16S> {
+    half2_t h[12];
+    float scale;
+    __device__ __forceinline__ double2 at(int k) const {
+        const float2 f = f16s_decode(h[k], scale);
+        return make_double2(f.x, f.y);
+    }
+};
 
 template <int PREC, bool BUF>
-__device__ __forceinline__ void load_column(const char* base, int32_t s, ColT<PREC> v[12]) {
+__device__ __forceinline__ void load_column(const char* base, int32_t s, RawCol<PREC>& r) {
     if constexpr (PREC == QDP_F16S) {
         const FieldRef<half2_t, BUF> f(base);
         const FieldRef<float, BUF> sc(base);
         const int64_t so = site_off<half2_t>(s, tile_bytes(1, 12, QDP_F16S));
-        const float scale = sc.load(12, so);
+        r.scale = sc.load(12, so);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = f16s_decode(f.load(k, so), scale);
+        for (int k = 0; k < 12; ++k) r.h[k] = f.load(k, so);
     } else {
-        const FieldRef<ColT<PREC>, BUF> f(base);
-        const int64_t so = site_off<ColT<PREC>>(s, tile_bytes(1, 12, PREC));
+        using T = typename std::remove_reference<decltype(r.v[0])>::type;
+        const FieldRef<T, BUF> f(base);
+        const int64_t so = site_off<T>(s, tile_bytes(1, 12, PREC));
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = f.load(k, so);
+        for (int k = 0; k < 12; ++k) r.v[k] = f.load(k, so);
     }
 }
-
-__device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
-__device__ __forceinline__ double2 to_d(double2 v) { return v; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -99,16 +109,23 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
             double2 G[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) G[x] = make_double2(0.0, 0.0);
+            // the six columns of this source spin (three colours of S2 and
+            // of S1) are requested before the arithmetic: one wait on memory
+            // per source spin
+            RawCol<PREC> c2[3], c1[3];
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                ColT<PREC> c2[12], c1[12];
-                load_column<PREC, BUF>(A.s2[3 * beta + b], s, c2);
-                load_column<PREC, BUF>(A.s1[3 * (beta ^ SIGMA) + b], s, c1);
+                load_column<PREC, BUF>(A.s2[3 * beta + b], s, c2[b]);
+                load_column<PREC, BUF>(A.s1[3 * (beta ^ SIGMA) + b], s, c1[b]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
 #pragma unroll
                 for (int alpha = 0; alpha < 4; ++alpha)
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        cmac_conj(G[alpha], to_d(c2[3 * alpha + c]), to_d(c1[3 * (alpha ^ SIGMA) + c]));
+                        cmac_conj(G[alpha], c2[b].at(3 * alpha + c), c1[b].at(3 * (alpha ^ SIGMA) + c));
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
