@@ -52,6 +52,8 @@ def _load():
     lib.or_smear.restype = ctypes.c_int32
     lib.or_meson.argtypes = [_i32p, _dp, _dp, _dp]
     lib.or_meson.restype = ctypes.c_int32
+    lib.or_meson_mom.argtypes = [_i32p, _dp, _dp, ctypes.c_int32, _i32p, _dp]
+    lib.or_meson_mom.restype = ctypes.c_int32
     lib.or_timeslice_sum.argtypes = [_i32p, ctypes.c_int32, _dp, _dp]
     lib.or_timeslice_sum.restype = None
     lib.or_norm2.argtypes = [ctypes.c_int64, _dp]
@@ -145,6 +147,23 @@ def meson(S1, S2, dims) -> np.ndarray:
                           _dptr(b.view(np.float64)), _dptr(out.view(np.float64)))
     if rc != 0:
         raise MemoryError("oracle meson: allocation failed")
+    return out
+
+
+def meson_mom(S1, S2, dims, moms) -> np.ndarray:
+    """Momentum-projected C_n(p, t), shape (nmom, 16, Lt) complex128, for the
+    integer momenta `moms` (sequence of (k0, k1, k2), p_i = 2 pi k_i / L_i)."""
+    a = _c128(S1)
+    b = _c128(S2)
+    V = volume(dims)
+    assert a.shape == (12, V, 4, 3) and b.shape == a.shape
+    k = np.ascontiguousarray(np.asarray(moms, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((k.shape[0], 16, int(dims[3])), dtype=np.complex128)
+    d = _dims(dims)
+    rc = _load().or_meson_mom(d.ctypes.data_as(_i32p), _dptr(a.view(np.float64)), _dptr(b.view(np.float64)),
+                              int(k.shape[0]), k.ctypes.data_as(_i32p), _dptr(out.view(np.float64)))
+    if rc != 0:
+        raise MemoryError("oracle meson_mom: allocation failed")
     return out
 
 

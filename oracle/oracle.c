@@ -270,16 +270,12 @@ static inline cplx prop_elem(const double* S, int64_t V, int64_t s, int row, int
     return c_make(p[0], p[1]);
 }
 
-int32_t or_meson(const int32_t d[4], const double* S1, const double* S2, double* out) {
+/* The 16 traces at every site: site_val[16 s + n]. */
+static void meson_site_values(const int32_t d[4], const double* S1, const double* S2, cplx* site_val) {
     const int64_t V = volume(d);
-    const int32_t Lt = d[3];
-    const int64_t Vs = V / Lt;
     cplx G[16][4][4];
     for (int n = 0; n < 16; ++n) gamma_n(n, G[n]);
     const double g5[4] = {1.0, 1.0, -1.0, -1.0};
-
-    cplx* site_val = (cplx*)malloc(sizeof(cplx) * 16 * (size_t)V);
-    if (!site_val) return -1;
 
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < V; ++s) {
@@ -315,6 +311,15 @@ int32_t or_meson(const int32_t d[4], const double* S1, const double* S2, double*
             site_val[16 * s + n] = tr;
         }
     }
+}
+
+int32_t or_meson(const int32_t d[4], const double* S1, const double* S2, double* out) {
+    const int64_t V = volume(d);
+    const int32_t Lt = d[3];
+    const int64_t Vs = V / Lt;
+    cplx* site_val = (cplx*)malloc(sizeof(cplx) * 16 * (size_t)V);
+    if (!site_val) return -1;
+    meson_site_values(d, S1, S2, site_val);
 
     /* Time-slice sums: sequential FP64 over lexicographic sites of each slice. */
     for (int n = 0; n < 16; ++n)
@@ -324,6 +329,39 @@ int32_t or_meson(const int32_t d[4], const double* S1, const double* S2, double*
             out[2 * (n * Lt + t)] = acc.re;
             out[2 * (n * Lt + t) + 1] = acc.im;
         }
+    free(site_val);
+    return 0;
+}
+
+/* Momentum-projected meson correlators: the same traces weighted by the     */
+/* plane wave exp(-i p.x) before the time-slice sum,                         */
+/*   C_n(p, t) = sum_{x : x_3 = t} exp(-i p.x) Tr[...],  p_i = 2 pi k_i / L_i */
+/* with x the absolute spatial coordinate.  moms holds nmom integer triples  */
+/* (k_0, k_1, k_2); out is [nmom][16][Lt][re, im].                           */
+int32_t or_meson_mom(const int32_t d[4], const double* S1, const double* S2, int32_t nmom, const int32_t* moms,
+                     double* out) {
+    const int64_t V = volume(d);
+    const int32_t Lt = d[3];
+    const int64_t Vs = V / Lt;
+    const double two_pi = 6.283185307179586476925286766559;
+    cplx* site_val = (cplx*)malloc(sizeof(cplx) * 16 * (size_t)V);
+    if (!site_val) return -1;
+    meson_site_values(d, S1, S2, site_val);
+    for (int32_t q = 0; q < nmom; ++q) {
+        const int32_t* k = moms + 3 * q;
+        for (int n = 0; n < 16; ++n)
+            for (int32_t t = 0; t < Lt; ++t) {
+                cplx acc = c_make(0.0, 0.0);
+                for (int64_t r = 0; r < Vs; ++r) {
+                    const int64_t x = r % d[0], y = (r / d[0]) % d[1], z = r / ((int64_t)d[0] * d[1]);
+                    const double px = two_pi * ((double)k[0] * x / d[0] + (double)k[1] * y / d[1] +
+                                                (double)k[2] * z / d[2]);
+                    acc = c_add(acc, c_mul(c_make(cos(px), -sin(px)), site_val[16 * (t * Vs + r) + n]));
+                }
+                out[2 * ((q * 16 + n) * Lt + t)] = acc.re;
+                out[2 * ((q * 16 + n) * Lt + t) + 1] = acc.im;
+            }
+    }
     free(site_val);
     return 0;
 }

@@ -393,6 +393,77 @@ def test_free_point_source_correlator_closed_form():
         assert np.count_nonzero(C[n, 1:]) == 0
 
 
+# --------------------------------------------------------------------------
+# Momentum-projected contraction
+# --------------------------------------------------------------------------
+
+def test_momentum_free_point_source_convolution():
+    """Unit links, 12-column point source: S(x) = phi(x) 1_12, so
+    C_n(p, t0) = 12 eps_n sum_x exp(-i p.x) phi(x)^2, which by the
+    convolution theorem is 12 eps_n Vs^-1 sum_q lambda(q)^N lambda(q - p)^N;
+    the momentum sum is over the Brillouin zone, not over sites."""
+    dims = (4, 6, 2, 4)
+    N = 5
+    S = oracle.smear(unit_links(dims), synth.point_source(dims, range(12)), dims, 0.25, N)
+    moms = [(0, 0, 0), (1, 0, 0), (0, 2, 1), (3, 5, 1), (-1, 1, 0)]
+    C = oracle.meson_mom(S, S, dims, moms)
+    L = dims[:3]
+    q = [2 * np.pi * np.arange(l) / l for l in L]
+    Q = np.meshgrid(*q, indexing="ij")
+    lam = 1 + 0.5 * (np.cos(Q[0]) + np.cos(Q[1]) + np.cos(Q[2]))
+    Vs = L[0] * L[1] * L[2]
+    for m, k in enumerate(moms):
+        shifted = np.roll(lam, shift=k, axis=(0, 1, 2))  # lambda(q - p)
+        expect = np.sum(lam ** N * shifted ** N) / Vs
+        for n in range(16):
+            assert abs(C[m, n, 0] - 12 * _epsilon(n) * expect) <= 1e-12 * lam.max() ** (2 * N)
+            assert np.count_nonzero(C[m, n, 1:]) == 0
+
+
+def test_momentum_zero_is_the_plain_correlator_and_translation_phase():
+    """p = 0 gives C_n(t); translating both propagators by a spatial vector d
+    multiplies C_n(p, t) by exp(-i p.d)."""
+    dims = (4, 2, 6, 3)
+    U = synth.su3_links(dims, 61)
+    S1 = oracle.smear(U, synth.gaussian_propagator(dims, 161), dims, 0.2, 3)
+    S2 = synth.gaussian_propagator(dims, 162)
+    moms = [(0, 0, 0), (1, 1, 1), (2, 0, -1), (-1, 1, 5)]
+    C = oracle.meson_mom(S1, S2, dims, moms)
+    C0 = oracle.meson(S1, S2, dims)
+    assert np.abs(C[0] - C0).max() <= 1e-14 * np.abs(C0).max()
+    d = (1, 1, 2)
+
+    def translate(S):  # S'(x) = S(x - d), column by column
+        out = []
+        for col in S:
+            for mu in range(3):
+                for _ in range(d[mu]):
+                    col = oracle.shift(col, dims, mu, -1)
+            out.append(col)
+        return np.stack(out)
+
+    Ct = oracle.meson_mom(translate(S1), translate(S2), dims, moms)
+    for m, k in enumerate(moms):
+        phase = np.exp(-2j * np.pi * sum(k[i] * d[i] / dims[i] for i in range(3)))
+        assert np.abs(Ct[m] - phase * C[m]).max() <= 1e-12 * np.abs(C0).max()
+
+
+def test_momentum_inverse_transform_recovers_the_origin():
+    """Summing C_n(p, t) over the whole Brillouin zone gives Vs times the
+    trace at the spatial origin of slice t (here read off by contracting
+    propagators that vanish everywhere else)."""
+    dims = (2, 4, 2, 3)
+    S1 = synth.gaussian_propagator(dims, 171)
+    S2 = synth.gaussian_propagator(dims, 172)
+    moms = [(a, b, c) for a in range(2) for b in range(4) for c in range(2)]
+    Csum = oracle.meson_mom(S1, S2, dims, moms).sum(axis=0)
+    Vs = 16
+    origin = np.zeros(synth.volume(dims), dtype=bool)
+    origin[np.arange(dims[3]) * Vs] = True
+    C_origin = oracle.meson(S1 * origin[None, :, None, None], S2 * origin[None, :, None, None], dims)
+    assert np.abs(Csum - Vs * C_origin).max() <= 1e-12 * np.abs(Csum).max()
+
+
 def test_config1_pion_is_column_norm_per_slice():
     """The one-column pion correlator C(t) = sum_x |psi(x, t)|^2 is the n = 15
     term restricted to column 0 (the other columns zero)."""
