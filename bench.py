@@ -40,6 +40,14 @@ HBM_PEAK_GBPS = 8000.0
 FLOP_PER_SITE_UPDATE = 1752
 
 
+# Algorithmic HBM bytes per site-update used for the roofline (the
+# measurement model of the workload definition): 12-column update, psi read
+# and written once per iteration, links read twice per iteration on the
+# checkerboard (once per subset).
+MODEL_BYTES_PER_SITE_UPDATE = {("F32", True): 228, ("F16S", True): 124, ("F32", False): 210,
+                               ("F16S", False): 114}
+
+
 def pass_bytes(V: int, prec: str, checkerboard: bool) -> float:
     """Algorithmic HBM bytes of one smearing launch over all 12 columns.
 
@@ -66,13 +74,14 @@ def setup_fields(q, lat, prec, V):
     return g, src, work
 
 
-def run_batched(q, torch, lat, prec, V, steps, warmup):
+def run_batched(q, torch, lat, prec, V, steps, warmup, mode=None):
     """Time `steps` full steps; returns a dict of timings and the correlator."""
     from paper_1111_5596_amd import qdpmi
 
+    mode = qdpmi.SMEAR_EVEN_ODD if mode is None else mode
     g, src, work = setup_fields(q, lat, prec, V)
     for _ in range(warmup):
-        q.smear_to(g, src, work, KAPPA, NITER, mode=qdpmi.SMEAR_EVEN_ODD)
+        q.smear_to(g, src, work, KAPPA, NITER, mode=mode)
         q.contract(work, work)
     stream = q.stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
@@ -82,7 +91,7 @@ def run_batched(q, torch, lat, prec, V, steps, warmup):
     corr = None
     for k in range(steps):
         ev[k][0].record(stream)
-        q.smear_to(g, src, work, KAPPA, NITER, mode=qdpmi.SMEAR_EVEN_ODD)
+        q.smear_to(g, src, work, KAPPA, NITER, mode=mode)
         ev[k][1].record(stream)
         corr = q.contract(work, work)  # synchronises: returns host data
         ev[k][2].record(stream)
@@ -134,6 +143,40 @@ def run_plain(q, torch, lat, V):
     return {"wall_s": wall, "corr": corr}
 
 
+def run_batch64(q, torch):
+    """The multi-lattice workload: 64 lattices drawn from 8^3x16 .. 24^3x48,
+    12-column point sources, kappa 0.25, N 30, FP32, one persistent launch per
+    iteration, then the pion correlator of each lattice.  Returns
+    (site-updates, seconds per step)."""
+    from paper_1111_5596_amd import synth
+
+    jobs, fields, su = [], [], 0
+    for l, dims in enumerate(synth.lattice_sizes_batch()):
+        lat = q.lattice(dims)
+        g = q.alloc(lat, "GAUGE", "F32")
+        q.fill_random_su3(g, 4001 + l)
+        src = [q.alloc(lat, "FERMION", "F32") for _ in range(12)]
+        for j, f in enumerate(src):
+            q.fill_point(f, 0, j // 3, j % 3)
+        dst = [q.alloc(lat, "FERMION", "F32") for _ in range(12)]
+        jobs.append((g, src, dst))
+        fields += [g] + src + dst
+        su += 12 * dims[0] * dims[1] * dims[2] * dims[3] * 30
+    q.smear_batch(jobs, KAPPA, 30)  # warm (graph build)
+    for _, _, dst in jobs:
+        q.contract(dst, dst, mask=1 << 15)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.smear_batch(jobs, KAPPA, 30)
+    for _, _, dst in jobs:
+        q.contract(dst, dst, mask=1 << 15)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for f in fields:
+        q.free(f)
+    return su, dt
+
+
 def copy_bandwidth(q, torch, lat):
     """Device copy of one F32 fermion field (qdp_eval dest = src): the plain
     copy kernel used to scale the HBM counters and as the attainable
@@ -154,6 +197,32 @@ def copy_bandwidth(q, torch, lat):
     q.free(a)
     q.free(b)
     return nbytes / (ms * 1e-3) / 1e9, nbytes, ms
+
+
+def kernel_source_digest() -> str:
+    """Hash of the sources of the profiled smearing kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("smear.hip", "device.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1111_5596_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the profiled kernel (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel calibration), if the committed
+    measurement was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "smear_f16s_48c96_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(full_steps_niter=NITER):
@@ -191,6 +260,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage batched run")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice batch workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -216,6 +286,12 @@ def main():
     if not args.no_fp32:
         fp32 = run_batched(q, torch, lat, "F32", V, max(1, args.steps // 2), 1)
         print(f"[bench] F32 step {fp32['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+    full = run_batched(q, torch, lat, "F16S", V, max(1, args.steps // 2), 1, mode=qdpmi.SMEAR_FULL)
+    print(f"[bench] F16S full-update step {full['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+    batch = None
+    if not args.no_batch:
+        batch = run_batch64(q, torch)
+        print(f"[bench] 64-lattice batch {batch[1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     plain = None
     if not args.no_plain:
         plain = run_plain(q, torch, lat, V)
@@ -227,7 +303,10 @@ def main():
 
     value = site_updates / (f16["ms_per_step"] * 1e-3)
     launch_ms = f16["smear_ms"] / launches
-    achieved = pass_bytes(V, "F16S", True) / (launch_ms * 1e-3) / 1e9
+    per_launch_units = 12 * V // 2  # site-updates of one checkerboard pass
+    model_bytes = MODEL_BYTES_PER_SITE_UPDATE[("F16S", True)] * per_launch_units
+    achieved = model_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
     out = {
         "metric": "smearing site-updates/s + achieved HBM GB/s; batched/mixed vs plain FP32",
         "value": value,
@@ -247,9 +326,12 @@ def main():
                    "lattice": list(DIMS), "columns": 12, "iterations": NITER, "storage": "F16S",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "smear_kernel<F16S> (one checkerboard pass, 12 columns)",
-                     "bytes_per_launch": pass_bytes(V, "F16S", True), "launch_ms": launch_ms},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "smear_kernel<F16S> (one checkerboard subset pass, 12 columns)",
+                     "bytes_per_launch": model_bytes, "units_per_launch": per_launch_units,
+                     "bytes_per_unit": MODEL_BYTES_PER_SITE_UPDATE[("F16S", True)], "launch_ms": launch_ms,
+                     "pass_minimum_bytes_per_launch": pass_bytes(V, "F16S", True),
+                     "pass_minimum_GBps": pass_bytes(V, "F16S", True) / (launch_ms * 1e-3) / 1e9},
         "smear_ms_per_step": f16["smear_ms"],
         "contract_ms_per_step": f16["contract_ms"],
         "smear_site_updates_per_s": site_updates / (f16["smear_ms"] * 1e-3),
@@ -258,6 +340,14 @@ def main():
         "copy_kernel_GBps": copy_gbps,
         "frac_of_copy_bandwidth": achieved / copy_gbps,
     }
+    out["f16s_full_update"] = {
+        "value": site_updates / (full["ms_per_step"] * 1e-3), "ms_per_step": full["ms_per_step"],
+        "smear_GBps_model": MODEL_BYTES_PER_SITE_UPDATE[("F16S", False)] * 12 * V / (full["smear_ms"] / NITER * 1e-3) / 1e9,
+        "launch_shape": list(full["shape"])}
+    if batch:
+        out["batch64_fp32"] = {"value": batch[0] / batch[1], "site_updates": batch[0], "ms": batch[1] * 1e3,
+                               "workload": "64 lattices from {8^3x16,12^3x24,16^3x32,24^3x48}, 12 columns, "
+                                           "N 30, one persistent launch per iteration + pion correlators"}
     if fp32:
         r32 = site_updates / (fp32["ms_per_step"] * 1e-3)
         l32 = fp32["smear_ms"] / launches

@@ -104,9 +104,12 @@ enum qdp_set_kind { QDP_SET_ALL = 0, QDP_SET_PARITY = 1, QDP_SET_TIMESLICE = 2 }
 enum qdp_assign { QDP_ASSIGN = 0, QDP_ADD_ASSIGN = 1, QDP_SUB_ASSIGN = 2, QDP_MUL_ASSIGN = 3 };
 
 enum qdp_smear_mode {
-    QDP_SMEAR_FULL = 0,    /* every site updated in one pass per iteration */
-    QDP_SMEAR_EVEN_ODD = 1 /* two passes per iteration (even, then odd sites),
-                              both reading the previous iterate */
+    QDP_SMEAR_FULL = 0,    /* every site updated in one launch per iteration
+                              (tiles of the two parities interleaved) */
+    QDP_SMEAR_EVEN_ODD = 1 /* two subset launches per iteration, even sites and
+                              odd sites, both reading the previous iterate;
+                              they depend on the previous iteration only, not
+                              on each other, so they may overlap in time */
 };
 
 /* Flags for qdp_init_opts.flags. */
@@ -165,6 +168,15 @@ qdp_status qdp_field_write(qdp_ctx* ctx, qdp_field f, const double* host, size_t
 
 /* Copy the field to a canonical host array (synchronises). */
 qdp_status qdp_field_read(qdp_ctx* ctx, qdp_field f, double* host, size_t n_doubles);
+
+/* Copy time slices t_begin .. t_end-1 of a field to a canonical host array
+ * of the sub-lattice Lx x Ly x Lz x (t_end - t_begin) (same per-site layout
+ * as qdp_field_read; for GAUGE the four directions of the sub-lattice one
+ * after another).  Only the device tiles holding those slices are copied.
+ * n_doubles must equal the sub-lattice's canonical size.  Synchronises.
+ * Errors: QDP_ERR_ARG (range or size). */
+qdp_status qdp_field_read_timeslices(qdp_ctx* ctx, qdp_field f, int32_t t_begin, int32_t t_end,
+                                     double* host, size_t n_doubles);
 
 /* Describe a field: type, precision, lattice, device bytes, residency
  * (1 = on device, 0 = spilled to host). */
@@ -319,6 +331,8 @@ typedef struct {
     uint64_t pool_high_water;
     uint64_t host_used;     /* pinned spill bytes in use */
     uint64_t n_fields;
+    uint64_t n_external;     /* live qdp_pool_malloc blocks */
+    uint64_t external_bytes; /* their total size */
 } qdp_cache_stats_t;
 
 /* Fill *out (synchronises). */
@@ -338,6 +352,29 @@ qdp_status qdp_set_pool_limit(qdp_ctx* ctx, size_t bytes);
 /* Fail the n-th device pool allocation from now (n >= 1) with
  * QDP_ERR_NOMEM, once; 0 disarms.  For tests of the failure paths. */
 qdp_status qdp_fault_alloc_after(qdp_ctx* ctx, int64_t n);
+
+/* ---------------------------------------------------------------------- */
+/* External allocations from the pool (QUDA-integration subsection and     */
+/* Figure 2: a solver library's device allocations are redirected to the   */
+/* pool manager, spilling LRU fields first when the pool is full, so that  */
+/* the library and the fields share one pool)                              */
+/* ---------------------------------------------------------------------- */
+
+/* Allocate `bytes` (> 0) bytes of device memory from the pool: *out gets a
+ * 256-byte aligned device pointer, contents undefined.  The block stays at
+ * that address until qdp_pool_free (it is never spilled or moved, and
+ * qdp_set_pool_limit below its end fails with QDP_ERR_STATE).  Making room
+ * may spill least-recently-used unpinned fields to pinned host memory (the
+ * copies are enqueued on the context stream).  Errors: QDP_ERR_ARG (bytes 0,
+ * null out), QDP_ERR_NOMEM (no room even with every field spilled; no
+ * allocation is made, *out untouched). */
+qdp_status qdp_pool_malloc(qdp_ctx* ctx, size_t bytes, void** out);
+
+/* Return a block of qdp_pool_malloc to the pool.  The block may be reused by
+ * the next allocation, so work on other streams that touches it must have
+ * finished (work on the context stream is ordered).  Errors: QDP_ERR_ARG (p
+ * is not a live block of qdp_pool_malloc). */
+qdp_status qdp_pool_free(qdp_ctx* ctx, void* p);
 
 /* Wait for all work enqueued on the context's stream. */
 qdp_status qdp_sync(qdp_ctx* ctx);

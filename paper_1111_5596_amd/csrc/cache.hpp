@@ -149,6 +149,12 @@ public:
     // spilled.
     qdp_status set_limit(size_t bytes) {
         if (bytes > dev_.capacity()) return QDP_ERR_ARG;
+        // a pinned entry (in use, or an external block) above the limit
+        // cannot move: refuse before changing anything
+        for (const auto& kv : entries_) {
+            const CacheEntry& e = kv.second;
+            if (e.on_device && e.pins && e.dev_off + OffsetPool::round_up(e.bytes) > bytes) return QDP_ERR_STATE;
+        }
         dev_.set_limit(bytes);
         for (auto& kv : entries_) {
             CacheEntry& e = kv.second;

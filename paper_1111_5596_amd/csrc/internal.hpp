@@ -67,6 +67,9 @@ struct Ctx {
     std::unordered_map<uint64_t, Field> fields;
     std::unordered_map<uint64_t, Lattice> lattices;
     uint64_t next_id = 1;
+    // qdp_pool_malloc blocks: device address -> cache entry id (pinned for life)
+    std::unordered_map<uintptr_t, uint64_t> external;
+    uint64_t external_bytes = 0;
 
     // small pinned buffer for results copied back to the host
     double* host_result = nullptr;

@@ -245,21 +245,26 @@ void to_device_layout(const Geometry& g, int32_t type, int32_t prec, const doubl
                 }
 }
 
-void from_device_layout(const Geometry& g, int32_t type, int32_t prec, const char* base,
-                        double* host) {
+// Convert slices t0..t1-1 to the canonical layout of that sub-lattice.
+// `at(off)` returns the host address holding device byte offset `off` of the
+// field image (only the tiles of the requested slices are read).
+template <typename At>
+void from_device_layout(const Geometry& g, int32_t type, int32_t prec, At at, double* host, int32_t t0,
+                        int32_t t1) {
     const TypeShape sh = type_shape(type);
-    for (int32_t t = 0; t < g.L[3]; ++t)
+    const int64_t Vsub = (int64_t)g.L[0] * g.L[1] * g.L[2] * (t1 - t0);
+    for (int32_t t = t0; t < t1; ++t)
         for (int32_t z = 0; z < g.L[2]; ++z)
             for (int32_t y = 0; y < g.L[1]; ++y)
                 for (int32_t x = 0; x < g.L[0]; ++x) {
-                    const int64_t s = x + (int64_t)g.L[0] * (y + (int64_t)g.L[1] * (z + (int64_t)g.L[2] * t));
+                    const int64_t s = x + (int64_t)g.L[0] * (y + (int64_t)g.L[1] * (z + (int64_t)g.L[2] * (t - t0)));
                     const int64_t c = cb_index(g, x, y, z, t);
                     for (int32_t r = 0; r < sh.nrec; ++r) {
                         float sc = 1.f;
                         if (prec == QDP_F16S)
-                            sc = *reinterpret_cast<const float*>(base + scale_offset(sh.nrec, sh.ncomp, r, c));
+                            sc = *reinterpret_cast<const float*>(at(scale_offset(sh.nrec, sh.ncomp, r, c)));
                         for (int32_t k = 0; k < sh.ncomp; ++k) {
-                            const char* p = base + comp_offset(sh.nrec, sh.ncomp, prec, r, k, c);
+                            const char* p = at(comp_offset(sh.nrec, sh.ncomp, prec, r, k, c));
                             double re, im;
                             if (prec == QDP_F64) {
                                 re = reinterpret_cast<const double*>(p)[0];
@@ -271,7 +276,8 @@ void from_device_layout(const Geometry& g, int32_t type, int32_t prec, const cha
                                 re = (double)((float)reinterpret_cast<const _Float16*>(p)[0] * sc);
                                 im = (double)((float)reinterpret_cast<const _Float16*>(p)[1] * sc);
                             }
-                            const size_t hi = host_index(g, type, s, r, k);
+                            const size_t hi = type == QDP_REAL ? (size_t)s
+                                                               : (((size_t)r * Vsub + s) * sh.ncomp + k) * 2;
                             host[hi] = re;
                             if (type != QDP_REAL) host[hi + 1] = im;
                         }
@@ -454,7 +460,55 @@ qdp_status qdp_field_read(qdp_ctx* ctx, qdp_field f, double* host, size_t n_doub
         release_field(ctx, f);
         if (e != hipSuccess) return hip_error(ctx, e, "field_read copy");
     }
-    from_device_layout(g, fd->type, fd->prec, staging.data(), host);
+    const char* img = staging.data();
+    from_device_layout(g, fd->type, fd->prec, [img](int64_t off) { return img + off; }, host, 0, g.L[3]);
+    return QDP_OK;
+    QDP_API_END(ctx)
+}
+
+qdp_status qdp_field_read_timeslices(qdp_ctx* ctx, qdp_field f, int32_t t_begin, int32_t t_end,
+                                     double* host, size_t n_doubles) {
+    if (!ctx || !host) return set_error(ctx, QDP_ERR_ARG, "null argument");
+    QDP_API_BEGIN
+    Field* fd = find_field(ctx, f);
+    if (!fd) return set_error(ctx, QDP_ERR_STATE, "unknown field handle");
+    const Geometry& g = find_lattice(ctx, fd->lattice)->geo;
+    if (t_begin < 0 || t_end > g.L[3] || t_begin >= t_end)
+        return set_error(ctx, QDP_ERR_ARG, "read_timeslices: bad slice range");
+    const TypeShape sh = type_shape(fd->type);
+    const int64_t Vsub = (int64_t)g.L[0] * g.L[1] * g.L[2] * (t_end - t_begin);
+    const size_t need = fd->type == QDP_REAL ? (size_t)Vsub : (size_t)Vsub * sh.nrec * sh.ncomp * 2;
+    if (n_doubles != need)
+        return set_error(ctx, QDP_ERR_ARG, "read_timeslices: expected %zu doubles, got %zu", need, n_doubles);
+    // the slices occupy checkerboard sites [p Vh + t_begin Vsh, p Vh + t_end Vsh) for
+    // p = 0, 1: copy the tiles of those two ranges into one compact staging buffer
+    const int64_t tb = tile_bytes(sh.nrec, sh.ncomp, fd->prec);
+    int64_t a[2], b[2];
+    for (int par = 0; par < 2; ++par) {
+        a[par] = (par * g.Vh + t_begin * g.Vsh) / 64;
+        b[par] = (par * g.Vh + t_end * g.Vsh + 63) / 64;
+    }
+    if (a[1] < b[0]) a[1] = b[0];  // tiny lattices: the two ranges share a tile
+    std::vector<char> staging((size_t)((b[0] - a[0] + b[1] - a[1]) * tb));
+    char* p;
+    QDP_CHECK(acquire_field(ctx, f, true, &p));
+    hipError_t e = hipMemcpyAsync(staging.data(), p + a[0] * tb, (size_t)((b[0] - a[0]) * tb),
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && b[1] > a[1])
+        e = hipMemcpyAsync(staging.data() + (b[0] - a[0]) * tb, p + a[1] * tb, (size_t)((b[1] - a[1]) * tb),
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    release_field(ctx, f);
+    if (e != hipSuccess) return hip_error(ctx, e, "read_timeslices copy");
+    const char* img = staging.data();
+    const int64_t a0 = a[0], b0 = b[0], a1 = a[1];
+    auto at = [=](int64_t off) {
+        const int64_t tile = off / tb;
+        const int64_t within = off - tile * tb;
+        const int64_t pos = tile < b0 ? tile - a0 : (b0 - a0) + (tile - a1);
+        return img + pos * tb + within;
+    };
+    from_device_layout(g, fd->type, fd->prec, at, host, t_begin, t_end);
     return QDP_OK;
     QDP_API_END(ctx)
 }
@@ -475,6 +529,8 @@ qdp_status qdp_cache_stats(qdp_ctx* ctx, qdp_cache_stats_t* out) {
     out->pool_high_water = ctx->cache.device_pool().high_water();
     out->host_used = ctx->cache.host_pool().used_bytes();
     out->n_fields = ctx->fields.size();
+    out->n_external = ctx->external.size();
+    out->external_bytes = ctx->external_bytes;
     return QDP_OK;
 }
 
@@ -498,6 +554,40 @@ qdp_status qdp_set_pool_limit(qdp_ctx* ctx, size_t bytes) {
     QDP_API_BEGIN
     if (bytes > ctx->pool_bytes) return set_error(ctx, QDP_ERR_ARG, "pool limit above capacity");
     return cache_status(ctx, ctx->cache.set_limit(bytes), "set_pool_limit");
+    QDP_API_END(ctx)
+}
+
+qdp_status qdp_pool_malloc(qdp_ctx* ctx, size_t bytes, void** out) {
+    if (!ctx || !out || bytes == 0) return set_error(ctx, QDP_ERR_ARG, "pool_malloc: bad argument");
+    QDP_API_BEGIN
+    const uint64_t id = ctx->next_id++;
+    QDP_CHECK(cache_status(ctx, ctx->cache.create(id, bytes), "pool_malloc"));
+    // pinned for the block's whole life: never chosen as a spill victim
+    qdp_status s = ctx->cache.acquire(id, false);
+    if (s != QDP_OK) {
+        ctx->cache.destroy(id);
+        return cache_status(ctx, s, "pool_malloc");
+    }
+    char* p = ctx->pool_base + ctx->cache.find(id)->dev_off;
+    ctx->external[reinterpret_cast<uintptr_t>(p)] = id;
+    ctx->external_bytes += bytes;
+    *out = p;
+    return QDP_OK;
+    QDP_API_END(ctx)
+}
+
+qdp_status qdp_pool_free(qdp_ctx* ctx, void* p) {
+    if (!ctx) return QDP_ERR_ARG;
+    QDP_API_BEGIN
+    auto it = ctx->external.find(reinterpret_cast<uintptr_t>(p));
+    if (it == ctx->external.end())
+        return set_error(ctx, QDP_ERR_ARG, "pool_free: %p is not a live pool_malloc block", p);
+    const uint64_t id = it->second;
+    ctx->external_bytes -= ctx->cache.find(id)->bytes;
+    ctx->cache.release(id);
+    ctx->cache.destroy(id);
+    ctx->external.erase(it);
+    return QDP_OK;
     QDP_API_END(ctx)
 }
 

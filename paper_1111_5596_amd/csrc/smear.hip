@@ -47,7 +47,7 @@ struct SmearLaunch {
     int32_t site_waves;  // wavefronts of sites per block
     int32_t col_groups;  // column groups per site
     int32_t xcd;         // XCD-aware block mapping
-    int32_t pad;
+    int32_t interleave;  // whole lattice: block 2b = even tile b, 2b+1 = odd tile b
     double kappa;
 };
 
@@ -309,7 +309,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
     int64_t b = blockIdx.x;
     if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
     if (b >= ln.nlogical) return;
-    tile_update<PREC, BUF>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.kappa);
+    if (ln.interleave) {
+        // the even tile and the odd tile with the same index are each other's
+        // neighbours: updating them together lets the L2 serve both
+        const int64_t parity = b & 1;
+        tile_update<PREC, BUF>(job, b >> 1, parity * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups, ln.kappa);
+    } else {
+        tile_update<PREC, BUF>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.kappa);
+    }
 }
 
 // Persistent multi-lattice kernel: a fixed grid walks a work list of
@@ -375,7 +382,10 @@ std::vector<void*> arg_pointers(Launch& L) {
     return p;
 }
 
-qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
+// Launch a sequence of kernels; consecutive groups of `width` launches are
+// independent of each other and each group depends on the whole previous
+// group (width 2: the even and odd passes of one smearing iteration).
+qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph, int width = 1) {
     if (ls.empty()) return QDP_OK;
     if (!use_graph || ls.size() < 2) {
         for (auto& L : ls) {
@@ -385,7 +395,7 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
         return QDP_OK;
     }
     // Graph cache keyed by every launch's function, shape and argument bytes.
-    std::string key;
+    std::string key(reinterpret_cast<const char*>(&width), sizeof width);
     for (auto& L : ls) {
         key.append(reinterpret_cast<const char*>(&L.func), sizeof(L.func));
         key.append(reinterpret_cast<const char*>(&L.grid), sizeof(L.grid));
@@ -403,8 +413,9 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
         }
         hipGraph_t graph;
         QDP_HIP(ctx, hipGraphCreate(&graph, 0));
-        hipGraphNode_t prev = nullptr;
-        for (auto& L : ls) {
+        std::vector<hipGraphNode_t> prev, cur;
+        for (size_t i = 0; i < ls.size(); ++i) {
+            Launch& L = ls[i];
             auto p = arg_pointers(L);
             hipKernelNodeParams np{};
             np.func = L.func;
@@ -414,12 +425,16 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
             np.kernelParams = p.data();
             np.extra = nullptr;
             hipGraphNode_t node;
-            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            hipError_t e = hipGraphAddKernelNode(&node, graph, prev.empty() ? nullptr : prev.data(), prev.size(), &np);
             if (e != hipSuccess) {
                 hipGraphDestroy(graph);
                 return hip_error(ctx, e, "hipGraphAddKernelNode");
             }
-            prev = node;
+            cur.push_back(node);
+            if ((int)cur.size() == width || i + 1 == ls.size()) {
+                prev.swap(cur);
+                cur.clear();
+            }
         }
         hipGraphExec_t exec;
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -464,13 +479,17 @@ void* smear_func(int prec, const qdp_launch_shape& sh, bool batch) {
                    : smear_func_buf<true>(prec, sh.waves_per_simd, batch);
 }
 
+// A pass over [begin, begin + count); count == V (the whole lattice) runs
+// the two parities' tiles interleaved.
 Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t count,
                           const qdp_launch_shape& sh, double kappa) {
     SmearLaunch ln{};
     ln.site_begin = begin;
     ln.site_count = count;
     const int64_t tile_sites = 64LL * sh.site_waves;
-    ln.nlogical = (count + tile_sites - 1) / tile_sites;
+    ln.interleave = (begin == 0 && count == job.g.V) ? 1 : 0;
+    ln.nlogical = ln.interleave ? 2 * ((job.g.Vh + tile_sites - 1) / tile_sites)
+                                : (count + tile_sites - 1) / tile_sites;
     ln.site_waves = sh.site_waves;
     ln.col_groups = sh.col_groups;
     ln.xcd = sh.xcd;
@@ -694,7 +713,7 @@ qdp_status smear_jacobi_impl(Ctx* ctx, uint64_t gauge, const uint64_t* src, cons
             const SmearJob& job = k == 1 ? first : (k % 2 == 0 ? to_dst : to_tmp);
             for (const Pass& p : passes) ls.push_back(make_single_launch(prec, job, p.begin, p.count, sh, kappa));
         }
-        QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH)));
+        QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH), (int)passes.size()));
         QDP_CHECK(check_launch(ctx, "smear kernel"));
     }
     if (n_iter % 2 == 1) {

@@ -76,7 +76,8 @@ class qdp_smear_job(ctypes.Structure):
 class qdp_cache_stats_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "hits", "misses", "spills", "fills", "bytes_spilled", "bytes_filled", "pool_capacity",
-        "pool_limit", "pool_used", "pool_high_water", "host_used", "n_fields")]
+        "pool_limit", "pool_used", "pool_high_water", "host_used", "n_fields", "n_external",
+        "external_bytes")]
 
 
 class qdp_launch_shape(ctypes.Structure):
@@ -102,6 +103,7 @@ SIGNATURES = {
     "qdp_field_write": (_i32, [_vp, _u64, _dp, _sz]),
     "qdp_field_read": (_i32, [_vp, _u64, _dp, _sz]),
     "qdp_field_info": (_i32, [_vp, _u64, _c.POINTER(qdp_field_info_t)]),
+    "qdp_field_read_timeslices": (_i32, [_vp, _u64, _i32, _i32, _dp, _sz]),
     "qdp_eval": (_i32, [_vp, _c.POINTER(qdp_expr), _u64, qdp_subset, _i32]),
     "qdp_shift": (_i32, [_vp, _u64, _u64, _i32, _i32, qdp_subset]),
     "qdp_sum_multi": (_i32, [_vp, _c.POINTER(qdp_expr), _i32, _dp, _sz]),
@@ -114,6 +116,8 @@ SIGNATURES = {
     "qdp_cache_evict_all": (_i32, [_vp]),
     "qdp_set_pool_limit": (_i32, [_vp, _sz]),
     "qdp_fault_alloc_after": (_i32, [_vp, _i64]),
+    "qdp_pool_malloc": (_i32, [_vp, _c.c_size_t, _c.POINTER(_vp)]),
+    "qdp_pool_free": (_i32, [_vp, _vp]),
     "qdp_sync": (_i32, [_vp]),
     "qdp_last_error": (_c.c_char_p, [_vp]),
     "qdp_fill_random": (_i32, [_vp, _u64, _i32, _u64, _i32, _dbl]),
@@ -266,6 +270,20 @@ class Context:
             return host.view(np.complex128).reshape(4, V, 3, 3)
         return host.view(np.complex128).reshape((V,) + CANONICAL[t])
 
+    def read_timeslices(self, f, t_begin, t_end):
+        """Canonical array of slices t_begin..t_end-1 (a sub-lattice)."""
+        lat, t, _ = self.field_meta[f]
+        Lx, Ly, Lz, _ = self.lattice_dims[lat]
+        Vsub = Lx * Ly * Lz * (t_end - t_begin)
+        n = Vsub if t == "REAL" else Vsub * NCOMP[t] * 2
+        host = np.empty(n, dtype=np.float64)
+        self.check(lib.qdp_field_read_timeslices(self.h, f, t_begin, t_end, host.ctypes.data_as(_dp), n))
+        if t == "REAL":
+            return host
+        if t == "GAUGE":
+            return host.view(np.complex128).reshape(4, Vsub, 3, 3)
+        return host.view(np.complex128).reshape((Vsub,) + CANONICAL[t])
+
     def info(self, f):
         out = qdp_field_info_t()
         self.check(lib.qdp_field_info(self.h, f, ctypes.byref(out)))
@@ -343,6 +361,23 @@ class Context:
 
     def fault_alloc_after(self, n):
         self.check(lib.qdp_fault_alloc_after(self.h, n))
+
+    def pool_malloc(self, nbytes):
+        """Device address (int) of `nbytes` bytes taken from the pool."""
+        p = ctypes.c_void_p()
+        self.check(lib.qdp_pool_malloc(self.h, nbytes, ctypes.byref(p)))
+        return p.value
+
+    def pool_free(self, ptr):
+        self.check(lib.qdp_pool_free(self.h, ctypes.c_void_p(ptr)))
+
+    def pool_view(self, ptr, nbytes):
+        """A uint8 tensor aliasing `nbytes` of the pool at device address `ptr`
+        (the pool is the context's own tensor)."""
+        off = ptr - self._pool.data_ptr()
+        if off < 0 or off + nbytes > self._pool.numel():
+            raise ValueError("address outside the pool")
+        return self._pool[off:off + nbytes]
 
     def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0):
         s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, 0)

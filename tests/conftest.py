@@ -22,6 +22,6 @@ def qdp():
         pytest.fail("GPU test collected on a machine without a GPU")
     from paper_1111_5596_amd import qdpmi
 
-    ctx = qdpmi.Context(pool_bytes=int(os.environ.get("QDP_TEST_POOL_BYTES", 16 << 30)))
+    ctx = qdpmi.Context(pool_bytes=int(os.environ.get("QDP_TEST_POOL_BYTES", 64 << 30)))
     yield ctx
     ctx.close()

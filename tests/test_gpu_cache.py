@@ -1,0 +1,202 @@
+"""GPU tests of the field cache: a pool too small for the working set forces
+LRU spills to pinned host memory and fills on use; results must stay bitwise
+equal to an unconstrained run, and failures must leave no partial state."""
+
+import numpy as np
+import pytest
+
+from paper_1111_5596_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(pool, spill, flags=0):
+    from paper_1111_5596_amd import qdpmi
+
+    return qdpmi.Context(pool_bytes=pool, host_spill_bytes=spill, flags=flags)
+
+
+def _run_chain(q, dims, U, psi):
+    lat = q.lattice(dims)
+    g = q.alloc(lat, "GAUGE", "F32")
+    q.write(g, U)
+    cols = []
+    for c in psi:
+        f = q.alloc(lat, "FERMION", "F32")
+        q.write(f, c)
+        cols.append(f)
+    q.smear(g, cols, 0.25, 6, mode=1)
+    C = q.contract(cols, cols)
+    return g, cols, C
+
+
+def test_spill_and_fill_keep_results_bitwise():
+    dims = (8, 8, 8, 4)
+    U = synth.su3_links(dims, 21)
+    psi = synth.gaussian_propagator(dims, 121)
+    col_bytes = 96 * synth.volume(dims)
+    big = _ctx(256 << 20, 0)
+    try:
+        g0, cols0, C0 = _run_chain(big, dims, U, psi)
+        ref = [big.read(f) for f in cols0]
+    finally:
+        big.close()
+    # pool for the links plus ~30 columns: the 12 inputs, 12 ping-pong partners
+    # and the other chain's fields cannot all stay resident
+    q = _ctx(int(30.5 * col_bytes) + 2 * 72 * 4 * synth.volume(dims), 64 << 20)
+    try:
+        g1, cols1, C1 = _run_chain(q, dims, U, psi)
+        g2, cols2, C2 = _run_chain(q, dims, U, psi)  # second chain evicts the first
+        st = q.cache_stats()
+        assert st["spills"] > 0, st
+        for f, r in zip(cols1, ref):  # first chain's fields come back from host
+            assert np.array_equal(q.read(f), r)
+        for f, r in zip(cols2, ref):
+            assert np.array_equal(q.read(f), r)
+        assert np.array_equal(C1, C0) and np.array_equal(C2, C0)
+        # re-using spilled fields in a computation fills them
+        q.smear(g1, cols1, 0.25, 1)
+        st2 = q.cache_stats()
+        assert st2["fills"] > 0 and st2["misses"] > 0, st2
+        assert st2["pool_high_water"] <= st2["pool_capacity"]
+    finally:
+        q.close()
+
+
+def test_explicit_evict_and_pool_limit():
+    dims = (4, 4, 4, 4)
+    q = _ctx(64 << 20, 16 << 20)
+    try:
+        lat = q.lattice(dims)
+        P = synth.gaussian_propagator(dims, 9, ncols=3)
+        fs = []
+        for c in P:
+            f = q.alloc(lat, "FERMION", "F64")
+            q.write(f, c)
+            fs.append(f)
+        q.evict(fs[1])
+        assert q.info(fs[1]).on_device == 0
+        assert np.array_equal(q.read(fs[1]), P[1])  # read straight from the host copy
+        q.eval([("field", fs[1])], fs[2])  # use fills it back
+        assert q.info(fs[1]).on_device == 1
+        assert np.array_equal(q.read(fs[2]), P[1])
+        q.evict_all()
+        assert all(q.info(f).on_device == 0 for f in fs)
+        q.set_pool_limit(q.info(fs[0]).bytes * 2 + 4096)
+        st = q.cache_stats()
+        assert st["pool_limit"] <= q.info(fs[0]).bytes * 2 + 4096
+        # computing with all three needs more than the limit: LRU spills make room
+        q.eval([("field", fs[0]), ("field", fs[1]), ("add",)], fs[2])
+        assert np.allclose(q.read(fs[2]), P[0] + P[1], rtol=0, atol=1e-15)
+    finally:
+        q.close()
+
+
+def test_nomem_and_fault_injection_leave_no_state():
+    from paper_1111_5596_amd.qdpmi import QdpError
+
+    dims = (4, 4, 4, 4)
+    q = _ctx(4 << 20, 0)
+    try:
+        lat = q.lattice(dims)
+        f = q.alloc(lat, "FERMION", "F64")
+        before = q.cache_stats()
+        with pytest.raises(QdpError, match="NOMEM"):
+            q.alloc(lat, "PROPAGATOR", "F64")  # 9.4 MB > pool, no spill area
+        q.fault_alloc_after(1)
+        with pytest.raises(QdpError, match="NOMEM"):
+            q.alloc(lat, "FERMION", "F64")
+        after = q.cache_stats()
+        assert after["pool_used"] == before["pool_used"] and after["n_fields"] == before["n_fields"]
+        g = q.alloc(lat, "FERMION", "F64")  # injection was one-shot
+        q.free(g)
+        q.free(f)
+        assert q.cache_stats()["pool_used"] == 0
+    finally:
+        q.close()
+
+
+def test_pool_malloc_spills_fields_and_stays_put():
+    """qdp_pool_malloc takes memory from the same pool as the fields: making
+    room spills LRU fields (whose contents survive), the block is never moved
+    or spilled while fields come and go, and errors leave no state."""
+    import torch
+
+    from paper_1111_5596_amd.qdpmi import QdpError
+
+    dims = (8, 8, 8, 8)
+    V = synth.volume(dims)
+    col_bytes = 192 * V  # FP64 FERMION
+    q = _ctx(8 * col_bytes + (1 << 20), 64 << 20)
+    try:
+        lat = q.lattice(dims)
+        P = synth.gaussian_propagator(dims, 31, ncols=6)
+        fs = []
+        for c in P:
+            f = q.alloc(lat, "FERMION", "F64")
+            q.write(f, c)
+            fs.append(f)
+        spills0 = q.cache_stats()["spills"]
+        nbytes = 3 * col_bytes
+        ptr = q.pool_malloc(nbytes)
+        st = q.cache_stats()
+        assert ptr % 256 == 0 and st["spills"] > spills0, st
+        assert st["n_external"] == 1 and st["external_bytes"] == nbytes
+        blk = q.pool_view(ptr, nbytes)
+        pattern = torch.arange(nbytes, dtype=torch.int64, device=blk.device).remainder_(251).to(torch.uint8)
+        blk.copy_(pattern)
+        # every field is still intact, and using them all cycles the cache
+        for _ in range(2):
+            for f, c in zip(fs, P):
+                assert np.array_equal(q.read(f), c)
+            for i in range(len(fs)):
+                q.eval([("field", fs[i]), ("real_const", 0.0), ("mul",)], fs[(i + 1) % len(fs)], assign="+=")
+        torch.cuda.synchronize()
+        assert torch.equal(blk, pattern)  # never moved, never overwritten
+        assert q.cache_stats()["n_external"] == 1
+        with pytest.raises(QdpError, match="NOMEM"):
+            q.pool_malloc(16 * col_bytes)
+        with pytest.raises(QdpError, match="ARG"):
+            q.pool_free(ptr + 256)
+        q.pool_free(ptr)
+        with pytest.raises(QdpError, match="ARG"):
+            q.pool_free(ptr)
+        st = q.cache_stats()
+        assert st["n_external"] == 0 and st["external_bytes"] == 0
+        for f in fs:
+            q.free(f)
+        assert q.cache_stats()["pool_used"] == 0
+    finally:
+        q.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-10), ("F32", 1e-5)])
+def test_cg_on_the_smearing_operator(qdp, prec, tol):
+    """Conjugate gradient on 1 + kappa H written in expressions and FP64 sums;
+    the solution is checked against the oracle's smearing step (M x = b)."""
+    import oracle
+    from paper_1111_5596_amd import solver
+
+    dims = (8, 6, 4, 4)
+    kappa = 0.12
+    U = synth.su3_links(dims, 41)
+    bh = synth.gaussian_propagator(dims, 141, ncols=1)[0]
+    lat = qdp.lattice(dims)
+    g = qdp.alloc(lat, "GAUGE", prec)
+    qdp.write(g, U)
+    b = qdp.alloc(lat, "FERMION", prec)
+    qdp.write(b, bh)
+    x = qdp.alloc(lat, "FERMION", prec)
+    qdp.write(x, np.zeros_like(bh))
+    ext = qdp.cache_stats()["n_external"]
+    try:
+        it, res = solver.cg_jacobi(qdp, g, b, x, kappa, tol=tol, maxiter=200)
+        assert 0 < it < 200 and res <= 2 * tol, (it, res)
+        xs = qdp.read(x)
+        Mx = oracle.smear_step(qdp.read(g), xs, dims, kappa)
+        bref = qdp.read(b)
+        assert np.linalg.norm(Mx - bref) <= 4 * tol * np.linalg.norm(bref)
+        assert qdp.cache_stats()["n_external"] == ext
+    finally:
+        for f in (g, b, x):
+            qdp.free(f)

@@ -199,3 +199,24 @@ def test_jacobi_expression_stencil(qdp, prec):
     assert np.linalg.norm(got - expect) <= tol * np.linalg.norm(expect)
     for f in (g, a, b):
         qdp.free(f)
+
+
+@pytest.mark.parametrize("ftype,prec", [("FERMION", "F32"), ("GAUGE", "F16S"), ("REAL", "F64"),
+                                        ("PROPAGATOR", "F64")])
+def test_read_timeslices_matches_full_read(qdp, ftype, prec):
+    dims = (6, 4, 2, 10)
+    lat = qdp.lattice(dims)
+    f = qdp.alloc(lat, ftype, prec)
+    V = synth.volume(dims)
+    shape = {"FERMION": (V, 4, 3), "GAUGE": (4, V, 3, 3), "REAL": (V,), "PROPAGATOR": (V, 4, 4, 3, 3)}[ftype]
+    a = rand(shape, 5)
+    qdp.write(f, a.real if ftype == "REAL" else a)
+    full = qdp.read(f)
+    Vs = 6 * 4 * 2
+    for t0, t1 in [(0, 1), (3, 7), (9, 10), (0, 10)]:
+        part = qdp.read_timeslices(f, t0, t1)
+        if ftype == "GAUGE":
+            assert np.array_equal(part, full[:, t0 * Vs:t1 * Vs])
+        else:
+            assert np.array_equal(part, full[t0 * Vs:t1 * Vs])
+    qdp.free(f)

@@ -1,0 +1,132 @@
+"""GPU parity at the benchmark configurations' full sizes, in the launch
+configuration bench.py times (device-generated inputs, autotuned shapes,
+graph replay).  The oracle computes sampled outputs: the smearing never
+mixes time slices, so one slice of a column is an independent oracle
+problem; the contraction of one slice is checked on the GPU's own smeared
+slice.  Properties that hold at any size are checked on every slice."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_5596_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"F32": 1e-5, "F16S": 2e-3}
+
+
+@pytest.mark.parametrize("prec", ["F16S", "F32"])
+def test_48cubed_96_smear_and_contract(qdp, prec):
+    """48^3 x 96, links seed 5, 12-column Gaussian propagator seed 105, kappa
+    0.25, N 100, even/odd passes, 16 bilinears."""
+    from paper_1111_5596_amd import qdpmi
+
+    dims = (48, 48, 48, 96)
+    V = synth.volume(dims)
+    sd = (48, 48, 48, 1)
+    t = 37
+    lat = qdp.lattice(dims)
+    g = qdp.alloc(lat, "GAUGE", prec)
+    qdp.fill_random_su3(g, 5)
+    src = [qdp.alloc(lat, "FERMION", prec) for _ in range(12)]
+    for j, f in enumerate(src):
+        qdp.fill_gaussian(f, 105, j, (24.0 * V) ** -0.5)
+    out = [qdp.alloc(lat, "FERMION", prec) for _ in range(12)]
+    try:
+        qdp.smear_to(g, src, out, 0.25, 100, mode=qdpmi.SMEAR_EVEN_ODD)
+        C = qdp.contract(out, out)
+        # sampled smearing parity: columns 0 and 7 on slice t, oracle from the
+        # host generator's copy of the same inputs
+        U = synth.su3_links(dims, 5, t_range=(t, t + 1))
+        P = synth.gaussian_propagator(dims, 105, t_range=(t, t + 1), columns=[0, 7])
+        ref = oracle.smear(U, P, sd, 0.25, 100)
+        got_slices = {}
+        for idx, j in enumerate([0, 7]):
+            got = qdp.read_timeslices(out[j], t, t + 1)
+            got_slices[j] = got
+            err = np.linalg.norm(got - ref[idx]) / np.linalg.norm(ref[idx])
+            assert err <= TOL[prec], (prec, j, err)
+        # contraction parity on slice t, oracle on the GPU's smeared slice
+        S = np.stack([qdp.read_timeslices(f, t, t + 1) for f in out])
+        Cref = oracle.meson(S, S, sd)[:, 0]
+        scale = abs(Cref[15].real)
+        assert np.max(np.abs(C[:, t] - Cref)) <= 1e-10 * scale
+        # properties on every slice: C_15 > 0 real, |C_n| <= C_15, Im C_n ~ 0
+        c15 = C[15].real
+        assert np.all(c15 > 0)
+        assert np.all(np.abs(C) <= c15[None, :] * (1 + 1e-9))
+        assert np.max(np.abs(C.imag)) <= 1e-9 * c15.max()
+        # FP64 time-slice sums of |psi|^2 agree with C_15
+        n2 = np.zeros(dims[3])
+        for f in out:
+            n2 += qdp.sum_multi([("field", f), ("local_norm2",)], "timeslice", 1, dims[3])[:, 0].real
+        assert np.max(np.abs(n2 - c15) / c15) <= 1e-9
+    finally:
+        for f in [g] + src + out:
+            qdp.free(f)
+
+
+def test_16cubed_32_point_source_pion_and_rho(qdp):
+    """16^3 x 32, links seed 2, 12-column point source smeared (N 50), pion
+    (n = 15) and rho (n = 1, 2, 4) from the smeared-smeared correlator; the
+    oracle smears the whole source slice (point source: only slice 0 is
+    non-zero)."""
+    dims = (16, 16, 16, 32)
+    sd = (16, 16, 16, 1)
+    lat = qdp.lattice(dims)
+    g = qdp.alloc(lat, "GAUGE", "F32")
+    qdp.fill_random_su3(g, 2)
+    cols = [qdp.alloc(lat, "FERMION", "F32") for _ in range(12)]
+    for j, f in enumerate(cols):
+        qdp.fill_point(f, 0, j // 3, j % 3)
+    try:
+        qdp.smear(g, cols, 0.25, 50)
+        C = qdp.contract(cols, cols)
+        U = synth.su3_links(dims, 2, t_range=(0, 1))
+        Sref = oracle.smear(U, synth.point_source(sd, range(12)), sd, 0.25, 50)
+        Cref = oracle.meson(Sref, Sref, sd)[:, 0]
+        c15 = Cref[15].real
+        for n in (15, 1, 2, 4):
+            assert abs(C[n, 0] - Cref[n]) <= 1e-5 * c15, n
+        assert np.count_nonzero(C[:, 1:]) == 0
+        rho = np.mean([C[n, 0] for n in (1, 2, 4)])
+        assert abs(rho - np.mean([Cref[n] for n in (1, 2, 4)])) <= 1e-5 * c15
+    finally:
+        for f in [g] + cols:
+            qdp.free(f)
+
+
+def test_batch_of_64_uneven_lattices(qdp):
+    """64 lattices drawn from {8^3x16, 12^3x24, 16^3x32, 24^3x48}, links seed
+    4001 + l, 12-column point sources, kappa 0.25, N 30, one persistent launch
+    per iteration; the pion correlator of every lattice, oracle-checked on the
+    first lattice of each size, zero off the source slice everywhere."""
+    sizes = synth.lattice_sizes_batch()
+    jobs, fields = [], []
+    first_of = {}
+    for l, dims in enumerate(sizes):
+        lat = qdp.lattice(dims)
+        g = qdp.alloc(lat, "GAUGE", "F32")
+        qdp.fill_random_su3(g, 4001 + l)
+        cols = [qdp.alloc(lat, "FERMION", "F32") for _ in range(12)]
+        for j, f in enumerate(cols):
+            qdp.fill_point(f, 0, j // 3, j % 3)
+        jobs.append((g, cols, cols))
+        fields.append((dims, g, cols))
+        first_of.setdefault(dims, l)
+    try:
+        qdp.smear_batch(jobs, 0.25, 30)
+        for l, (dims, g, cols) in enumerate(fields):
+            C = qdp.contract(cols, cols, mask=1 << 15)
+            assert C[15, 0].real > 0 and np.count_nonzero(C[15, 1:]) == 0
+            if first_of[dims] == l:
+                sd = dims[:3] + (1,)
+                U = synth.su3_links(dims, 4001 + l, t_range=(0, 1))
+                Sref = oracle.smear(U, synth.point_source(sd, range(12)), sd, 0.25, 30)
+                ref = oracle.meson(Sref, Sref, sd)[15, 0].real
+                assert abs(C[15, 0].real - ref) <= 1e-5 * ref, dims
+    finally:
+        for dims, g, cols in fields:
+            for f in [g] + cols:
+                qdp.free(f)

@@ -181,3 +181,29 @@ def test_fault_injection_and_swap(hl):
     assert c.verify(1, 2) == 0 and c.verify(2, 1) == 0
     assert c.destroy_field(1) == OK and c.destroy_field(1) == ERR_STATE
     assert c.check() == 0
+
+
+def test_external_block_spills_fields_and_pins_the_limit(hl):
+    """An external allocation (pinned for life, as qdp_pool_malloc makes it)
+    spills LRU fields to make room, is never chosen as a victim, and a pool
+    limit below its end is refused without changing anything."""
+    c = Cache(hl, 4096 * 4, 4096 * 4)
+    for i in range(1, 4):
+        assert c.create_field(i, 4096) == OK
+        c.write(i, i)
+    assert c.create_field(100, 4096 * 2) == OK and c.acquire(100, 0) == OK  # the external block
+    k = c.counters()
+    # 1 and 2, the least recently used, made a contiguous hole
+    assert k["spills"] == 2 and not c.info(1)["on_device"] and not c.info(2)["on_device"]
+    # more demand spills fields, never the block
+    for i in (1, 2, 3):
+        assert c.acquire(i, 1) == OK and c.verify(i, i) == 0
+        c.release(i)
+        assert c.info(100)["on_device"] and c.info(100)["pins"] == 1
+    before = (c.counters()["limit"], [c.info(i)["dev_off"] for i in (100,)])
+    end = c.info(100)["dev_off"] + 4096 * 2
+    assert c.set_limit(end - 4096) == ERR_STATE
+    assert (c.counters()["limit"], [c.info(i)["dev_off"] for i in (100,)]) == before
+    assert c.create_field(101, 4096 * 3) == ERR_NOMEM  # cannot fit beside the pinned block
+    c.release(100)
+    assert c.destroy_field(100) == OK and c.check() == 0
