@@ -54,6 +54,8 @@ def _load():
     lib.or_meson.restype = ctypes.c_int32
     lib.or_meson_mom.argtypes = [_i32p, _dp, _dp, ctypes.c_int32, _i32p, _dp]
     lib.or_meson_mom.restype = ctypes.c_int32
+    lib.or_nucleon.argtypes = [_i32p, _dp, _dp, ctypes.c_int32, _dp]
+    lib.or_nucleon.restype = ctypes.c_int32
     lib.or_timeslice_sum.argtypes = [_i32p, ctypes.c_int32, _dp, _dp]
     lib.or_timeslice_sum.restype = None
     lib.or_norm2.argtypes = [ctypes.c_int64, _dp]
@@ -164,6 +166,22 @@ def meson_mom(S1, S2, dims, moms) -> np.ndarray:
                               int(k.shape[0]), k.ctypes.data_as(_i32p), _dptr(out.view(np.float64)))
     if rc != 0:
         raise MemoryError("oracle meson_mom: allocation failed")
+    return out
+
+
+def nucleon(Su, Sd, dims, parity=1) -> np.ndarray:
+    """Proton two-point function C(t), shape (Lt,) complex128, with the
+    parity projector (1 + parity gamma_4)/2; Su, Sd have shape (12, V, 4, 3)."""
+    a = _c128(Su)
+    b = _c128(Sd)
+    V = volume(dims)
+    assert a.shape == (12, V, 4, 3) and b.shape == a.shape and parity in (1, -1)
+    out = np.zeros(int(dims[3]), dtype=np.complex128)
+    d = _dims(dims)
+    rc = _load().or_nucleon(d.ctypes.data_as(_i32p), _dptr(a.view(np.float64)), _dptr(b.view(np.float64)),
+                            int(parity), _dptr(out.view(np.float64)))
+    if rc != 0:
+        raise MemoryError("oracle nucleon: allocation failed")
     return out
 
 

@@ -367,6 +367,96 @@ int32_t or_meson_mom(const int32_t d[4], const double* S1, const double* S2, int
 }
 
 /* ------------------------------------------------------------------------ */
+/* Nucleon two-point function (the baryon part of the hadron spectrum).      */
+/*                                                                           */
+/* Interpolators (proton, u u d):                                            */
+/*   chi_g(x)     = eps_{abc} (Cg5)_{rs} u^a_r(x) d^b_s(x) u^c_g(x)          */
+/*   chibar_g'(0) = eps_{a'b'c'} ubar^{c'}_g' dbar^{b'}_s' G'_{s'r'} ubar^{a'}_r' */
+/* with C = gamma_2 gamma_4 (so C gamma_mu C^-1 = -gamma_mu^T) and           */
+/* G' = gamma_4 (Cg5)^dagger gamma_4^T = -Cg5, which makes chibar the Dirac  */
+/* adjoint of chi.  With S = <q qbar> (S_u = U, S_d = D; sink (spin,colour)  */
+/* rows, source columns) Wick's theorem gives a direct and an exchange term  */
+/*   <chi_g chibar_g'> = eps eps' (Cg5)_{rs} G'_{s'r'} D^{bb'}_{ss'}         */
+/*        [ U^{aa'}_{rr'} U^{cc'}_{gg'} - U^{ac'}_{rg'} U^{ca'}_{gr'} ],     */
+/* projected with P = (1 + sign gamma_4)/2: C(t) = sum_{x:x_3=t}             */
+/* sum_{g g'} P_{g'g} <chi_g(x) chibar_g'(0)>.  Written with M^{bb'} =       */
+/* Cg5 D^{bb'} G' this is                                                    */
+/*   eps eps' { Tr[P U^{cc'}] sum_{rr'} U^{aa'}_{rr'} M_{rr'}                */
+/*              - sum_{rr'} (U^{ac'} P U^{ca'})_{rr'} M_{rr'} }.             */
+/* out is [Lt][re, im].                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Spin block X^{ab}_{rr'} = S[(r a),(r' b)] of a propagator at site s. */
+static void spin_block(const double* S, int64_t V, int64_t s, int a, int b, cplx X[4][4]) {
+    for (int r = 0; r < 4; ++r)
+        for (int rp = 0; rp < 4; ++rp) X[r][rp] = prop_elem(S, V, s, 3 * r + a, 3 * rp + b);
+}
+
+int32_t or_nucleon(const int32_t d[4], const double* Su, const double* Sd, int32_t parity, double* out) {
+    const int64_t V = volume(d);
+    const int32_t Lt = d[3];
+    const int64_t Vs = V / Lt;
+    static const int perms[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+    static const double psign[6] = {1, 1, 1, -1, -1, -1};
+    cplx g2[4][4], g4[4][4], g5[4][4], Cm[4][4], Cg5[4][4], Gp[4][4], P[4][4];
+    gamma_n(2, g2);
+    gamma_n(8, g4);
+    gamma_n(15, g5);
+    mat4_mul(g2, g4, Cm);
+    mat4_mul(Cm, g5, Cg5);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            Gp[i][j] = c_scale(-1.0, Cg5[i][j]);
+            P[i][j] = c_scale(0.5 * parity, g4[i][j]);
+            if (i == j) P[i][j].re += 0.5;
+        }
+    cplx* site_val = (cplx*)malloc(sizeof(cplx) * (size_t)V);
+    if (!site_val) return -1;
+
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < V; ++s) {
+        cplx U[3][3][4][4], D[3][3][4][4];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                spin_block(Su, V, s, a, b, U[a][b]);
+                spin_block(Sd, V, s, a, b, D[a][b]);
+            }
+        cplx total = c_make(0.0, 0.0);
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                const int a = perms[i][0], b = perms[i][1], c = perms[i][2];
+                const int ap = perms[j][0], bp = perms[j][1], cp = perms[j][2];
+                const double sg = psign[i] * psign[j];
+                cplx T[4][4], M[4][4], PU[4][4], W[4][4];
+                mat4_mul(Cg5, D[b][bp], T);
+                mat4_mul(T, Gp, M);
+                cplx trPU = c_make(0.0, 0.0);
+                mat4_mul(P, U[c][cp], PU);
+                for (int r = 0; r < 4; ++r) trPU = c_add(trPU, PU[r][r]);
+                mat4_mul(U[a][cp], P, T);
+                mat4_mul(T, U[c][ap], W);
+                cplx direct = c_make(0.0, 0.0), exch = c_make(0.0, 0.0);
+                for (int r = 0; r < 4; ++r)
+                    for (int rp = 0; rp < 4; ++rp) {
+                        direct = c_add(direct, c_mul(U[a][ap][r][rp], M[r][rp]));
+                        exch = c_add(exch, c_mul(W[r][rp], M[r][rp]));
+                    }
+                const cplx term = c_add(c_mul(trPU, direct), c_scale(-1.0, exch));
+                total = c_add(total, c_scale(sg, term));
+            }
+        site_val[s] = total;
+    }
+    for (int32_t t = 0; t < Lt; ++t) {
+        cplx acc = c_make(0.0, 0.0);
+        for (int64_t k = 0; k < Vs; ++k) acc = c_add(acc, site_val[t * Vs + k]);
+        out[2 * t] = acc.re;
+        out[2 * t + 1] = acc.im;
+    }
+    free(site_val);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sums (global and time-slice), FP64, sequential over lexicographic sites.  */
 /* ------------------------------------------------------------------------ */
 

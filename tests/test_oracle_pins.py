@@ -464,6 +464,108 @@ def test_momentum_inverse_transform_recovers_the_origin():
     assert np.abs(Csum - Vs * C_origin).max() <= 1e-12 * np.abs(Csum).max()
 
 
+# --------------------------------------------------------------------------
+# Nucleon two-point function
+# --------------------------------------------------------------------------
+
+# DeGrand-Rossi gamma_1..gamma_4 written out (independent of the oracle's tables)
+_DR = [np.array(m, dtype=np.complex128) for m in (
+    [[0, 0, 0, 1j], [0, 0, 1j, 0], [0, -1j, 0, 0], [-1j, 0, 0, 0]],
+    [[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]],
+    [[0, 0, 1j, 0], [0, 0, 0, -1j], [-1j, 0, 0, 0], [0, 1j, 0, 0]],
+    [[0, 0, 1, 0], [0, 0, 0, 1], [1, 0, 0, 0], [0, 1, 0, 0]])]
+
+
+def _levi_civita():
+    eps = np.zeros((3, 3, 3))
+    for (a, b, c), sg in [((0, 1, 2), 1), ((1, 2, 0), 1), ((2, 0, 1), 1), ((0, 2, 1), -1), ((2, 1, 0), -1),
+                          ((1, 0, 2), -1)]:
+        eps[a, b, c] = sg
+    return eps
+
+
+def _nucleon_by_wick(Su, Sd, dims, parity):
+    """Proton correlator from the interpolators by Wick's theorem, with no
+    factorisation: for chi = eps (u^T Cg5 d) u and chibar its Dirac adjoint,
+    <u1 d2 u3 ubar3' dbar2' ubar1'> = D(2,2') det[[U(1,1'), U(1,3')], [U(3,1'), U(3,3')]],
+    every index tuple summed with einsum."""
+    g1, g2, g3, g4 = _DR
+    g5 = g1 @ g2 @ g3 @ g4
+    C = g2 @ g4
+    assert np.allclose(C @ g1 @ np.linalg.inv(C), -g1.T) and np.allclose(C @ g4 @ np.linalg.inv(C), -g4.T)
+    Gsnk = C @ g5
+    Gsrc = g4 @ Gsnk.conj().T @ g4.T  # chibar = chi^dagger gamma_4
+    P = 0.5 * (np.eye(4) + parity * g4)
+    eps = _levi_civita()
+    V = synth.volume(dims)
+    # U[x, r, a, r', a'] = S[(r a), (r' a')] = component (r, a) of column 3 r' + a'
+    U = np.transpose(Su.reshape(4, 3, V, 4, 3), (2, 3, 4, 0, 1))
+    D = np.transpose(Sd.reshape(4, 3, V, 4, 3), (2, 3, 4, 0, 1))
+    # sink colours a b c, spins r s g; source colours A B C, spins R S G
+    direct = np.einsum("abc,rs,ABC,SR,xraRA,xsbSB,xgcGC,Gg->x", eps, Gsnk, eps, Gsrc, U, D, U, P, optimize=True)
+    exch = np.einsum("abc,rs,ABC,SR,xraGC,xsbSB,xgcRA,Gg->x", eps, Gsnk, eps, Gsrc, U, D, U, P, optimize=True)
+    site = direct - exch
+    return site.reshape(dims[3], -1).sum(axis=1)
+
+
+@pytest.mark.parametrize("parity", [1, -1])
+def test_nucleon_matches_unfactorised_wick_contraction(parity):
+    dims = (2, 2, 4, 3)
+    Su = synth.gaussian_propagator(dims, 181)
+    Sd = synth.gaussian_propagator(dims, 182)
+    got = oracle.nucleon(Su, Sd, dims, parity)
+    ref = _nucleon_by_wick(Su, Sd, dims, parity)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_nucleon_free_point_source_closed_form():
+    """Unit links, 12-column point source: S(x) = phi(x) 1_12 and the two
+    Wick terms give 48 + 12 = 60 phi(x)^3 for either parity, so
+    C(t0) = 60 sum_x phi^3 = 60 Vs^-2 sum_{q1,q2} lambda(q1)^N lambda(q2)^N lambda(q1+q2)^N."""
+    dims = (4, 6, 2, 4)
+    N = 4
+    S = oracle.smear(unit_links(dims), synth.point_source(dims, range(12)), dims, 0.25, N)
+    L = dims[:3]
+    Q = np.meshgrid(*[2 * np.pi * np.arange(l) / l for l in L], indexing="ij")
+    lam = (1 + 0.5 * (np.cos(Q[0]) + np.cos(Q[1]) + np.cos(Q[2]))) ** N
+    Vs = L[0] * L[1] * L[2]
+    flat = lam.reshape(-1)
+    idx = np.indices(L).reshape(3, -1)
+    total = 0.0
+    for i in range(Vs):  # q1 + q2 mod L
+        k = (idx[:, i:i + 1] + idx) % np.array(L)[:, None]
+        total += flat[i] * np.sum(flat * lam[k[0], k[1], k[2]])
+    expect = 60 * total / Vs ** 2
+    for parity in (1, -1):
+        C = oracle.nucleon(S, S, dims, parity)
+        assert abs(C[0] - expect) <= 1e-12 * expect
+        assert np.count_nonzero(C[1:]) == 0
+
+
+def test_nucleon_gauge_invariance_and_parity_sum():
+    """eps eps' is SU(3) invariant: C(t) is unchanged under S(x) -> g(x) S(x);
+    the two parity projections add up to the unprojected trace (P = 1),
+    which the unfactorised contraction supplies."""
+    dims = (4, 2, 2, 3)
+    Su = synth.gaussian_propagator(dims, 191)
+    Sd = synth.gaussian_propagator(dims, 192)
+    g = synth.gauge_transform(dims, 9191)
+    C = oracle.nucleon(Su, Sd, dims, 1)
+    Cg = oracle.nucleon(gauge_rotate_fermions(g, Su), gauge_rotate_fermions(g, Sd), dims, 1)
+    assert np.abs(C - Cg).max() <= 1e-13 * np.abs(C).max()
+    Cm = oracle.nucleon(Su, Sd, dims, -1)
+    unproj = _nucleon_by_wick(Su, Sd, dims, 1) + _nucleon_by_wick(Su, Sd, dims, -1)
+    assert np.abs(C + Cm - unproj).max() <= 1e-13 * np.abs(unproj).max()
+    # the pin has teeth: a contraction that used D^{b'b} for D^{bb'} (sink and
+    # source colour of d exchanged) is not invariant
+    def colour_t(S):
+        return np.transpose(S.reshape(4, 3, -1, 4, 3), (0, 4, 2, 3, 1)).reshape(S.shape)
+
+    Ct = oracle.nucleon(Su, colour_t(Sd), dims, 1)
+    Ctg = oracle.nucleon(gauge_rotate_fermions(g, Su), colour_t(gauge_rotate_fermions(g, Sd)), dims, 1)
+    assert np.abs(Ct - Ctg).max() > 1e-3 * np.abs(Ct).max()
+
+
 def test_config1_pion_is_column_norm_per_slice():
     """The one-column pion correlator C(t) = sum_x |psi(x, t)|^2 is the n = 15
     term restricted to column 0 (the other columns zero)."""
