@@ -314,6 +314,43 @@ qdp_status qdp_smear_jacobi_batch(qdp_ctx* ctx, const qdp_smear_job* jobs, int32
 qdp_status qdp_hadron_contract(qdp_ctx* ctx, const qdp_field* S1, const qdp_field* S2,
                                uint32_t gamma_mask, int32_t t0, int32_t j_decay, double* out);
 
+/* Momentum-projected meson correlators (the hadron spectrum's plane-wave
+ * projections, HAD of section 5):
+ *   C_n(p, t) = sum_{x: x_3 = t} exp(-i p.x) Tr[ g5 S2^dagger g5 Gamma_n S1 Gamma_n ](x)
+ * with p_i = 2 pi k_i / L_i and x = (x, y, z) the site's absolute spatial
+ * coordinates.  moms: host array of nmom >= 1 integer triples (k_0, k_1,
+ * k_2), any sign (taken modulo L_i).  The traces are formed as in
+ * qdp_hadron_contract; the plane wave multiplies each site's FP64 traces
+ * before the FP64 slice sums.  out: nmom * 16 * Lt * 2 doubles,
+ * out[((q * 16 + n) * Lt + t') * 2 + k], momentum slowest; n outside the
+ * mask gives 0.  Cost: one read of S1 and S2 per four momenta.
+ * Synchronises.  Errors: as qdp_hadron_contract; QDP_ERR_ARG (nmom < 1,
+ * null moms). */
+qdp_status qdp_hadron_contract_mom(qdp_ctx* ctx, const qdp_field* S1, const qdp_field* S2,
+                                   uint32_t gamma_mask, const int32_t* moms, int32_t nmom, int32_t t0,
+                                   int32_t j_decay, double* out);
+
+/* ---------------------------------------------------------------------- */
+/* Baryon contractions (the baryon part of the hadron spectrum, HAD of     */
+/* section 5)                                                              */
+/* ---------------------------------------------------------------------- */
+
+enum qdp_baryon_kind { QDP_BARYON_PROTON = 0 };
+
+/* Proton two-point function with parity projection,
+ *   C(t) = sum_{x: x_3 = t} sum_{g g'} P_{g'g} < chi_g(x) chibar_g'(0) >,
+ *   chi = eps_abc (u_a^T C g5 d_b) u_c,  chibar = chi^dagger gamma_4,
+ *   P = (1 + parity gamma_4) / 2,  C = gamma_2 gamma_4 (DeGrand-Rossi),
+ * evaluated by Wick's theorem with Su = <u ubar> and Sd = <d dbar> (12
+ * FERMION columns each, same layout as qdp_hadron_contract; Sd may equal
+ * Su): a direct and an exchange term, no overall fermion sign.  Values are
+ * decoded to FP64; products and sums are FP64.  out: Lt * 2 doubles,
+ * out[t' * 2 + k] with t' = (t - t0) mod Lt.  Synchronises.  Errors:
+ * QDP_ERR_ARG (parity not +-1), QDP_ERR_UNSUPPORTED (kind, j_decay != 3,
+ * mixed precisions), QDP_ERR_TYPE, QDP_ERR_LATTICE. */
+qdp_status qdp_baryon_contract(qdp_ctx* ctx, const qdp_field* Su, const qdp_field* Sd, int32_t kind,
+                               int32_t parity, int32_t t0, int32_t j_decay, double* out);
+
 /* ---------------------------------------------------------------------- */
 /* Field cache (section 4.1 and Figure 2)                                  */
 /* ---------------------------------------------------------------------- */
@@ -414,9 +451,10 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
  * waves_per_simd selects the kernel variant compiled for that occupancy
  * (0, 2 or 3; 0 = compiler default; FP64 always uses 0), flat = 1 uses
  * 64-bit flat addresses instead of buffer addressing (forced on when a field
- * is 4 GiB or larger).  Every shape computes bitwise-identical results.  qdp_smear_set_shape forces a
- * shape (site_waves = 0 returns to autotuning); qdp_smear_get_shape reports
- * the shape the last smearing call used. */
+ * is 4 GiB or larger).  Every shape computes bitwise-identical results.
+ * qdp_smear_set_shape forces a shape (site_waves = 0 returns to
+ * autotuning); qdp_smear_get_shape reports the shape the last smearing call
+ * used.  `reserved` must be 0. */
 typedef struct {
     int32_t site_waves;
     int32_t col_groups;

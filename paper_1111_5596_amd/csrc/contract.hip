@@ -12,6 +12,8 @@
 // and C_n = sum_{a,b} P_n[a] Q_n[b] G_sigma[a][b] with P_n[a] = s_a Gamma_n[a, sigma a],
 // Q_n[b] = s_b Gamma_n[sigma b, b], s = diag(g5).  One wavefront of a block
 // handles one sigma for 64 sites; the four wavefronts read the same sites.
+// Momentum projection weights each site's traces by exp(-i p.x) before the
+// slice sum; one launch carries up to four momenta.
 // Products and sums are FP64 (propagators grow like 2^N under smearing and
 // |S|^2 leaves the FP32 range).  The time-slice sums are two-stage with a
 // fixed order: bitwise repeatable.
@@ -26,6 +28,33 @@
 
 namespace qdpmi {
 
+// DeGrand-Rossi gamma_1..gamma_4 as signed permutations: row r has its one
+// nonzero entry i^code[r] in column perm[r].  constexpr, so that the device
+// code's index arithmetic on them folds at compile time.
+struct SignedPerm {
+    int perm[4];
+    int code[4];
+};
+constexpr SignedPerm kGammaBasis[4] = {
+    {{3, 2, 1, 0}, {1, 1, 3, 3}},  // gamma_1
+    {{3, 2, 1, 0}, {2, 0, 0, 2}},  // gamma_2
+    {{2, 3, 0, 1}, {1, 3, 3, 1}},  // gamma_3
+    {{2, 3, 0, 1}, {0, 0, 0, 0}},  // gamma_4
+};
+constexpr SignedPerm sp_mul(const SignedPerm& A, const SignedPerm& B) {
+    SignedPerm C{};
+    for (int r = 0; r < 4; ++r) {
+        C.perm[r] = B.perm[A.perm[r]];
+        C.code[r] = (A.code[r] + B.code[A.perm[r]]) & 3;
+    }
+    return C;
+}
+constexpr SignedPerm kGamma5 =
+    sp_mul(sp_mul(sp_mul(kGammaBasis[0], kGammaBasis[1]), kGammaBasis[2]), kGammaBasis[3]);
+// charge conjugation C = gamma_2 gamma_4 times gamma_5
+constexpr SignedPerm kCg5 = sp_mul(sp_mul(kGammaBasis[1], kGammaBasis[3]), kGamma5);
+constexpr SignedPerm kGamma4 = kGammaBasis[3];
+
 struct GammaDev {
     int8_t perm[4][4];     // sigma -> spin permutation
     int8_t members[4][4];  // sigma -> n values
@@ -37,9 +66,10 @@ struct ContractArgs {
     Geometry g;
     const char* s1[12];
     const char* s2[12];
-    double* partial;  // [Lt][nchunks][16][2]
+    double* partial;  // [Lt][nchunks][momenta of the launch][16][2]
     int32_t nchunks;
     int32_t pad;
+    int32_t mom[4][3];  // integer momenta k of the launch, p_i = 2 pi k_i / L_i
 };
 
 // One 12-component column at one checkerboard site, as loaded: FP64 and FP32
@@ -90,12 +120,31 @@ __device__ __forceinline__ double2 unit_phase(int code) {
     return make_double2(code == 0 ? 1.0 : (code == 2 ? -1.0 : 0.0), code == 1 ? 1.0 : (code == 3 ? -1.0 : 0.0));
 }
 
+// exp(-i p.x) for integer momentum k at spatial coordinates c: the phase
+// angle is reduced exactly to a fraction num / (Lx Ly Lz) of a turn first.
+__device__ __forceinline__ double2 plane_wave(const Geometry& g, const int32_t k[3], const int32_t c[4]) {
+    const int64_t M = (int64_t)g.L[0] * g.L[1] * g.L[2];
+    int64_t num = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        int64_t r = ((int64_t)k[i] * c[i]) % g.L[i];
+        if (r < 0) r += g.L[i];
+        num += r * (M / g.L[i]);
+    }
+    num %= M;
+    double sn, cs;
+    sincospi(-2.0 * ((double)num / (double)M), &sn, &cs);
+    return make_double2(cs, sn);
+}
+
 // Sites of one slice chunk for the Klein-group element SIGMA (spin
 // permutation a -> a ^ SIGMA).  The source spin beta is the outer loop so
-// only one column of G and the four correlators stay in registers.
-template <int PREC, bool BUF, int SIGMA>
+// only one column of G and the four correlators stay in registers.  NMOM = 0:
+// zero momentum, C[m] accumulates the traces directly; NMOM > 0: a site's
+// traces are complete first, then C[4 q + m] += exp(-i p_q.x) trace_m.
+template <int PREC, bool BUF, int SIGMA, int NMOM>
 __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDev& gd, int t, int chunk, int lane,
-                                            double2 C[4]) {
+                                            double2* C) {
     const int64_t Vsh = A.g.Vsh;
     const int64_t Vs = 2 * Vsh;
     int n[4];
@@ -104,8 +153,11 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
     for (int64_t l = (int64_t)chunk * 64 + lane; l < Vs; l += (int64_t)A.nchunks * 64) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
+        double2 site_tr[4];
 #pragma unroll
-        for (int beta = 0; beta < 4; ++beta) {
+        for (int m = 0; m < 4; ++m) site_tr[m] = make_double2(0.0, 0.0);
+        double2* acc = NMOM > 0 ? site_tr : C;
+        auto source_spin = [&](int beta) {
             double2 G[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) G[x] = make_double2(0.0, 0.0);
@@ -132,31 +184,51 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
 #pragma unroll
                 for (int alpha = 0; alpha < 4; ++alpha) {
                     const double2 ph = unit_phase(gd.pcode[n[m]][alpha] + gd.qcode[n[m]][beta]);
-                    cmac(C[m], ph, G[alpha]);
+                    cmac(acc[m], ph, G[alpha]);
                 }
+            }
+        };
+        if constexpr (NMOM > 0) {
+            // kept rolled: unrolled, the compiler hoists several source
+            // spins' loads and spills them when the momentum tail follows
+#pragma unroll 1
+            for (int beta = 0; beta < 4; ++beta) source_spin(beta);
+        } else {
+#pragma unroll
+            for (int beta = 0; beta < 4; ++beta) source_spin(beta);
+        }
+        if constexpr (NMOM > 0) {
+            int32_t c[4];
+            cb_coords(A.g, s, c);
+#pragma unroll
+            for (int q = 0; q < NMOM; ++q) {
+                const double2 w = plane_wave(A.g, A.mom[q], c);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) cmac(C[4 * q + m], w, site_tr[m]);
             }
         }
     }
 }
 
-template <int PREC, bool BUF>
+template <int PREC, bool BUF, int NMOM>
 __global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd) {
+    constexpr int NQ = NMOM > 0 ? NMOM : 1;
     const int t = blockIdx.y;
     const int chunk = blockIdx.x;
     const int sigma = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    double2 C[4];
+    double2 C[4 * NQ];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) C[m] = make_double2(0.0, 0.0);
+    for (int m = 0; m < 4 * NQ; ++m) C[m] = make_double2(0.0, 0.0);
     switch (sigma) {
-        case 0: meson_sites<PREC, BUF, 0>(a, gd, t, chunk, lane, C); break;
-        case 1: meson_sites<PREC, BUF, 1>(a, gd, t, chunk, lane, C); break;
-        case 2: meson_sites<PREC, BUF, 2>(a, gd, t, chunk, lane, C); break;
-        default: meson_sites<PREC, BUF, 3>(a, gd, t, chunk, lane, C); break;
+        case 0: meson_sites<PREC, BUF, 0, NMOM>(a, gd, t, chunk, lane, C); break;
+        case 1: meson_sites<PREC, BUF, 1, NMOM>(a, gd, t, chunk, lane, C); break;
+        case 2: meson_sites<PREC, BUF, 2, NMOM>(a, gd, t, chunk, lane, C); break;
+        default: meson_sites<PREC, BUF, 3, NMOM>(a, gd, t, chunk, lane, C); break;
     }
-    __shared__ double red[4][4][2];
+    __shared__ double red[4][4 * NQ][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 4 * NQ; ++m) {
         const double re = wave_sum(C[m].x);
         const double im = wave_sum(C[m].y);
         if (lane == 0) {
@@ -165,60 +237,236 @@ __global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd)
         }
     }
     __syncthreads();
-    if (threadIdx.x < 16) {
-        const int sg = threadIdx.x >> 2, m = threadIdx.x & 3;
+    if (threadIdx.x < 16 * NQ) {
+        const int q = threadIdx.x >> 4, sg = (threadIdx.x >> 2) & 3, m = threadIdx.x & 3;
         const int n = gd.members[sg][m];
-        double* out = a.partial + (((int64_t)t * a.nchunks + chunk) * 16 + n) * 2;
-        out[0] = red[sg][m][0];
-        out[1] = red[sg][m][1];
+        double* out = a.partial + ((((int64_t)t * a.nchunks + chunk) * NQ + q) * 16 + n) * 2;
+        out[0] = red[sg][4 * q + m][0];
+        out[1] = red[sg][4 * q + m][1];
     }
 }
 
-// out[(n * Lt + (t - t0 mod Lt)) * 2 + k] = sum over chunks, fixed order.
-__global__ void meson_finish(const double* __restrict__ partial, int32_t Lt, int32_t nchunks,
+// out[((q * 16 + n) * Lt + (t - t0 mod Lt)) * 2 + k] = sum over chunks, fixed
+// order, for the nq momenta of a launch (nq = 1 at zero momentum).
+__global__ void meson_finish(const double* __restrict__ partial, int32_t Lt, int32_t nchunks, int32_t nq,
                              uint32_t mask, int32_t t0, double* __restrict__ out) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 16 * Lt) return;
-    const int n = idx / Lt, t = idx % Lt;
+    if (idx >= nq * 16 * Lt) return;
+    const int q = idx / (16 * Lt), n = (idx / Lt) % 16, t = idx % Lt;
     double re = 0.0, im = 0.0;
     if (mask & (1u << n)) {
         for (int c = 0; c < nchunks; ++c) {
-            const double* p = partial + (((int64_t)t * nchunks + c) * 16 + n) * 2;
+            const double* p = partial + ((((int64_t)t * nchunks + c) * nq + q) * 16 + n) * 2;
             re += p[0];
             im += p[1];
         }
     }
     const int tr = ((t - t0) % Lt + Lt) % Lt;
-    out[(n * Lt + tr) * 2] = re;
-    out[(n * Lt + tr) * 2 + 1] = im;
+    out[((q * 16 + n) * Lt + tr) * 2] = re;
+    out[((q * 16 + n) * Lt + tr) * 2 + 1] = im;
+}
+
+// ---------------------------------------------------------------------------
+// Proton two-point function (the baryon part of HAD):
+//   C(t) = sum_{x: x_3 = t} sum_{g g'} P_{g'g} <chi_g(x) chibar_g'(0)>,
+//   chi = eps_abc (u_a^T Cg5 d_b) u_c, chibar its Dirac adjoint (so the source
+//   diquark matrix is G' = -Cg5), P = (1 + parity gamma_4) / 2.
+// With spin blocks X^{aa'}_{rr'} = S[(r a),(r' a')] and M^{bb'} = Cg5 D^{bb'} G',
+// Wick's direct and exchange terms summed against eps eps' collapse, for the
+// two colours {x < y} other than b and {x' < y'} other than b', to
+//   C = sum_{b b'} s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ],
+//   f(X, Y) = Tr[P Y] <X, M> + Tr[P X] <Y, M> + <X P Y, M> + <Y P X, M>,
+// where <A, B> = sum_{rr'} A_{rr'} B_{rr'} and s_b is the sign of the colour
+// permutation (x, b, y).  One thread per site, nine (b, b') steps each
+// reading five spin blocks; values decoded to FP64, products and sums FP64.
+// ---------------------------------------------------------------------------
+
+struct BaryonArgs {
+    Geometry g;
+    const char* su[12];
+    const char* sd[12];
+    double* partial;  // [Lt][nchunks][2]
+    int32_t nchunks;
+    int32_t parity;
+};
+
+// z * i^k for a wave-uniform k.
+__device__ __forceinline__ double2 times_ik(double2 z, int k) {
+    switch (k & 3) {
+        case 0: return z;
+        case 1: return make_double2(-z.y, z.x);
+        case 2: return make_double2(-z.x, -z.y);
+        default: return make_double2(z.y, -z.x);
+    }
+}
+
+// X[r][r'] = component (r, a) of column 3 r' + ap at checkerboard site s.
+template <int PREC, bool BUF>
+__device__ __forceinline__ void load_block(const char* const* cols, int a, int ap, int32_t s, double2 X[4][4]) {
+#pragma unroll
+    for (int rp = 0; rp < 4; ++rp) {
+        const char* base = cols[3 * rp + ap];
+        if constexpr (PREC == QDP_F16S) {
+            const FieldRef<half2_t, BUF> f(base);
+            const FieldRef<float, BUF> sc(base);
+            const int64_t so = site_off<half2_t>(s, tile_bytes(1, 12, QDP_F16S));
+            const float scale = sc.load(12, so);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 v = f16s_decode(f.load(3 * r + a, so), scale);
+                X[r][rp] = make_double2(v.x, v.y);
+            }
+        } else {
+            using T = typename std::conditional<PREC == QDP_F64, double2, float2>::type;
+            const FieldRef<T, BUF> f(base);
+            const int64_t so = site_off<T>(s, tile_bytes(1, 12, PREC));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const T v = f.load(3 * r + a, so);
+                X[r][rp] = make_double2(v.x, v.y);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double2 cmul(double2 u, double2 v) {
+    double2 z = make_double2(0.0, 0.0);
+    cmac(z, u, v);
+    return z;
+}
+
+// Tr[P Y] with P = 1/2 + hp gamma_4 (hp = parity / 2).
+__device__ __forceinline__ double2 trace_p(const double2 Y[4][4], double hp) {
+    double2 d = make_double2(0.0, 0.0), o = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        d.x += Y[g][g].x;
+        d.y += Y[g][g].y;
+        const double2 z = times_ik(Y[kGamma4.perm[g]][g], kGamma4.code[g]);
+        o.x += z.x;
+        o.y += z.y;
+    }
+    return make_double2(0.5 * d.x + hp * o.x, 0.5 * d.y + hp * o.y);
+}
+
+__device__ __forceinline__ double2 inner_plain(const double2 A[4][4], const double2 B[4][4]) {
+    double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cmac(z, A[r][c], B[r][c]);
+    return z;
+}
+
+// <X P Y, M> = sum_{r, g} (X P)_{rg} (Y M^T)_{gr}.
+__device__ __forceinline__ double2 xpy_m(const double2 X[4][4], const double2 Y[4][4], const double2 M[4][4],
+                                        double hp) {
+    double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        // column g of X P: 1/2 X[r][g] + hp sum_{g'} X[r][g'] gamma_4[g'][g]
+        // (gamma_4[g'][g] nonzero for g = gperm[g'])
+        int gs = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (kGamma4.perm[k] == g) gs = k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double2 ym = make_double2(0.0, 0.0);  // (Y M^T)_{g r}
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cmac(ym, Y[g][c], M[r][c]);
+            const double2 xg = times_ik(X[r][gs], kGamma4.code[gs]);
+            const double2 xp = make_double2(0.5 * X[r][g].x + hp * xg.x, 0.5 * X[r][g].y + hp * xg.y);
+            cmac(z, xp, ym);
+        }
+    }
+    return z;
+}
+
+__device__ __forceinline__ double2 pair_term(const double2 X[4][4], const double2 Y[4][4], const double2 M[4][4],
+                                            double hp) {
+    double2 f = cmul(trace_p(Y, hp), inner_plain(X, M));
+    cmac(f, trace_p(X, hp), inner_plain(Y, M));
+    const double2 a = xpy_m(X, Y, M, hp);
+    const double2 b = xpy_m(Y, X, M, hp);
+    return make_double2(f.x + a.x + b.x, f.y + a.y + b.y);
+}
+
+template <int PREC, bool BUF>
+__global__ __launch_bounds__(256) void nucleon_kernel(BaryonArgs A) {
+    const int t = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int64_t Vsh = A.g.Vsh;
+    const int64_t Vs = 2 * Vsh;
+    const double hp = 0.5 * A.parity;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
+        const int64_t p = l >= Vsh ? 1 : 0;
+        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
+#pragma unroll 1
+        for (int bb = 0; bb < 9; ++bb) {
+            const int b = bb / 3, bp = bb % 3;
+            const int x = b == 0 ? 1 : 0, y = b == 2 ? 1 : 2;
+            const int xp = bp == 0 ? 1 : 0, yp = bp == 2 ? 1 : 2;
+            // (x, b, y) is an even permutation of (0, 1, 2) only for b = 1
+            const double sg = (b == 1 ? 1.0 : -1.0) * (bp == 1 ? 1.0 : -1.0);
+            double2 M[4][4];
+            {
+                double2 D[4][4];
+                load_block<PREC, BUF>(A.sd, b, bp, s, D);
+                // M = Cg5 D G' with G' = -Cg5:
+                // M[r][perm[q]] = -i^(code[r] + code[q]) D[perm[r]][q]
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        M[r][kCg5.perm[q]] = times_ik(D[kCg5.perm[r]][q], kCg5.code[r] + kCg5.code[q] + 2);
+            }
+            double2 X[4][4], Y[4][4];
+            load_block<PREC, BUF>(A.su, x, xp, s, X);
+            load_block<PREC, BUF>(A.su, y, yp, s, Y);
+            const double2 f1 = pair_term(X, Y, M, hp);
+            load_block<PREC, BUF>(A.su, x, yp, s, X);
+            load_block<PREC, BUF>(A.su, y, xp, s, Y);
+            const double2 f2 = pair_term(X, Y, M, hp);
+            acc.x += sg * (f1.x - f2.x);
+            acc.y += sg * (f1.y - f2.y);
+        }
+    }
+    __shared__ double red[4][2];
+    const double re = wave_sum(acc.x), im = wave_sum(acc.y);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = re;
+        red[w][1] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* out = A.partial + ((int64_t)t * A.nchunks + chunk) * 2;
+        out[0] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+        out[1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    }
+}
+
+// out[(t - t0 mod Lt) * 2 + k] = sum over chunks, fixed order.
+__global__ void nucleon_finish(const double* __restrict__ partial, int32_t Lt, int32_t nchunks, int32_t t0,
+                               double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Lt) return;
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        re += partial[((int64_t)t * nchunks + c) * 2];
+        im += partial[((int64_t)t * nchunks + c) * 2 + 1];
+    }
+    const int tr = ((t - t0) % Lt + Lt) % Lt;
+    out[2 * tr] = re;
+    out[2 * tr + 1] = im;
 }
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
-// DeGrand-Rossi gamma_1..gamma_4 as signed permutations: row r has its one
-// nonzero entry i^code[r] in column perm[r].
-namespace {
-struct SignedPerm {
-    int perm[4];
-    int code[4];
-};
-const SignedPerm kGammaBasis[4] = {
-    {{3, 2, 1, 0}, {1, 1, 3, 3}},  // gamma_1
-    {{3, 2, 1, 0}, {2, 0, 0, 2}},  // gamma_2
-    {{2, 3, 0, 1}, {1, 3, 3, 1}},  // gamma_3
-    {{2, 3, 0, 1}, {0, 0, 0, 0}},  // gamma_4
-};
-SignedPerm sp_mul(const SignedPerm& A, const SignedPerm& B) {
-    SignedPerm C;
-    for (int r = 0; r < 4; ++r) {
-        C.perm[r] = B.perm[A.perm[r]];
-        C.code[r] = (A.code[r] + B.code[A.perm[r]]) & 3;
-    }
-    return C;
-}
-}  // namespace
 
 void build_gamma_tables(Ctx* ctx) {
     const int klein[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
@@ -255,21 +503,27 @@ int phase_code(const double ph[2]) {
     return 3;
 }
 
-template <bool BUF>
+constexpr int kMomPerLaunch = 4;
+
+template <bool BUF, int NMOM>
 void* meson_func_buf(int prec) {
     switch (prec) {
-        case QDP_F64: return reinterpret_cast<void*>(&meson_kernel<QDP_F64, BUF>);
-        case QDP_F32: return reinterpret_cast<void*>(&meson_kernel<QDP_F32, BUF>);
-        default: return reinterpret_cast<void*>(&meson_kernel<QDP_F16S, BUF>);
+        case QDP_F64: return reinterpret_cast<void*>(&meson_kernel<QDP_F64, BUF, NMOM>);
+        case QDP_F32: return reinterpret_cast<void*>(&meson_kernel<QDP_F32, BUF, NMOM>);
+        default: return reinterpret_cast<void*>(&meson_kernel<QDP_F16S, BUF, NMOM>);
     }
 }
 
-void* meson_func(int prec, bool buf) { return buf ? meson_func_buf<true>(prec) : meson_func_buf<false>(prec); }
+void* meson_func(int prec, bool buf, bool mom) {
+    if (mom) return buf ? meson_func_buf<true, kMomPerLaunch>(prec) : meson_func_buf<false, kMomPerLaunch>(prec);
+    return buf ? meson_func_buf<true, 0>(prec) : meson_func_buf<false, 0>(prec);
+}
 }  // namespace
 
 qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
-                                int32_t t0, int32_t j_decay, double* out) {
+                                int32_t t0, int32_t j_decay, const int32_t* moms, int32_t nmom, double* out) {
     if (j_decay != 3) return set_error(ctx, QDP_ERR_UNSUPPORTED, "contract: only j_decay = 3 (time)");
+    if (nmom < 0 || (nmom > 0 && !moms)) return set_error(ctx, QDP_ERR_ARG, "contract: bad momentum list");
     uint64_t lat = 0;
     int32_t prec = -1;
     for (int side = 0; side < 2; ++side)
@@ -300,10 +554,14 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
         a.s2[c] = p;
     }
     a.nchunks = (int32_t)nchunks;
+    const bool mom = nmom > 0;
+    const int32_t nq = mom ? kMomPerLaunch : 1;  // momenta per launch
+    const int32_t nlaunch = mom ? (nmom + kMomPerLaunch - 1) / kMomPerLaunch : 1;
     PoolTemp scratch;
-    const size_t partial_bytes = sizeof(double) * 2 * 16 * (size_t)Lt * nchunks;
-    const size_t out_bytes = sizeof(double) * 2 * 16 * (size_t)Lt;
-    QDP_CHECK(scratch.alloc(ctx, (int64_t)(partial_bytes + out_bytes + 256)));
+    const size_t partial_bytes = sizeof(double) * 2 * 16 * (size_t)nq * Lt * nchunks;
+    const size_t launch_out_bytes = sizeof(double) * 2 * 16 * (size_t)nq * Lt;
+    const size_t out_bytes = sizeof(double) * 2 * 16 * (size_t)Lt * (mom ? nmom : 1);
+    QDP_CHECK(scratch.alloc(ctx, (int64_t)(partial_bytes + launch_out_bytes * nlaunch + 256)));
     a.partial = reinterpret_cast<double*>(scratch.ptr());
     double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
 
@@ -321,13 +579,90 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
 
     void* args[] = {&a, &gd};
     const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
-    QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256), args, 0,
-                                 ctx->stream));
-    QDP_CHECK(check_launch(ctx, "meson kernel"));
-    const int nthreads = 16 * Lt;
-    hipLaunchKernelGGL(meson_finish, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
-                       (int32_t)nchunks, mask, t0, d_out);
-    QDP_CHECK(check_launch(ctx, "meson finish kernel"));
+    for (int32_t L = 0; L < nlaunch; ++L) {
+        for (int q = 0; q < kMomPerLaunch; ++q)
+            for (int i = 0; i < 3; ++i) {
+                const int32_t k = L * kMomPerLaunch + q;
+                a.mom[q][i] = (mom && k < nmom) ? moms[3 * k + i] : 0;
+            }
+        QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256),
+                                     args, 0, ctx->stream));
+        QDP_CHECK(check_launch(ctx, "meson kernel"));
+        const int nthreads = nq * 16 * Lt;
+        hipLaunchKernelGGL(meson_finish, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
+                           (int32_t)nchunks, nq, mask, t0, d_out + (size_t)L * nq * 16 * Lt * 2);
+        QDP_CHECK(check_launch(ctx, "meson finish kernel"));
+    }
+    double* host;
+    QDP_CHECK(host_result_buffer(ctx, out_bytes, &host));
+    QDP_HIP(ctx, hipMemcpyAsync(host, d_out, out_bytes, hipMemcpyDeviceToHost, ctx->stream));
+    QDP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::memcpy(out, host, out_bytes);
+    return QDP_OK;
+}
+
+namespace {
+template <bool BUF>
+void* nucleon_func_buf(int prec) {
+    switch (prec) {
+        case QDP_F64: return reinterpret_cast<void*>(&nucleon_kernel<QDP_F64, BUF>);
+        case QDP_F32: return reinterpret_cast<void*>(&nucleon_kernel<QDP_F32, BUF>);
+        default: return reinterpret_cast<void*>(&nucleon_kernel<QDP_F16S, BUF>);
+    }
+}
+}  // namespace
+
+qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd, int32_t kind, int32_t parity,
+                                int32_t t0, int32_t j_decay, double* out) {
+    if (j_decay != 3) return set_error(ctx, QDP_ERR_UNSUPPORTED, "baryon: only j_decay = 3 (time)");
+    if (kind != QDP_BARYON_PROTON) return set_error(ctx, QDP_ERR_UNSUPPORTED, "baryon: unknown kind %d", kind);
+    if (parity != 1 && parity != -1) return set_error(ctx, QDP_ERR_ARG, "baryon: parity must be +1 or -1");
+    uint64_t lat = 0;
+    int32_t prec = -1;
+    for (int side = 0; side < 2; ++side)
+        for (int c = 0; c < 12; ++c) {
+            Field* f = find_field(ctx, side ? Sd[c] : Su[c]);
+            if (!f) return set_error(ctx, QDP_ERR_STATE, "baryon: unknown column handle");
+            if (f->type != QDP_FERMION) return set_error(ctx, QDP_ERR_TYPE, "baryon: columns must be FERMION");
+            if (lat && f->lattice != lat) return set_error(ctx, QDP_ERR_LATTICE, "baryon: columns on different lattices");
+            if (prec >= 0 && f->prec != prec)
+                return set_error(ctx, QDP_ERR_UNSUPPORTED, "baryon: all 24 columns must share one precision");
+            lat = f->lattice;
+            prec = f->prec;
+        }
+    const Geometry g = find_lattice(ctx, lat)->geo;
+    const int32_t Lt = g.L[3];
+    const int64_t Vs = 2 * g.Vsh;
+    int64_t nchunks = (8192 + Lt - 1) / Lt;
+    nchunks = std::max<int64_t>(1, std::min<int64_t>(nchunks, (Vs + 255) / 256));
+
+    PinSet pins(ctx);
+    BaryonArgs a{};
+    a.g = g;
+    for (int c = 0; c < 12; ++c) {
+        char* p;
+        QDP_CHECK(pins.add(Su[c], true, &p));
+        a.su[c] = p;
+        QDP_CHECK(pins.add(Sd[c], true, &p));
+        a.sd[c] = p;
+    }
+    a.nchunks = (int32_t)nchunks;
+    a.parity = parity;
+
+    PoolTemp scratch;
+    const size_t partial_bytes = sizeof(double) * 2 * (size_t)Lt * nchunks;
+    const size_t out_bytes = sizeof(double) * 2 * (size_t)Lt;
+    QDP_CHECK(scratch.alloc(ctx, (int64_t)(partial_bytes + out_bytes + 256)));
+    a.partial = reinterpret_cast<double*>(scratch.ptr());
+    double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
+    void* args[] = {&a};
+    const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
+    QDP_HIP(ctx, hipLaunchKernel(buf ? nucleon_func_buf<true>(prec) : nucleon_func_buf<false>(prec),
+                                 dim3((unsigned)nchunks, (unsigned)Lt), dim3(256), args, 0, ctx->stream));
+    QDP_CHECK(check_launch(ctx, "nucleon kernel"));
+    hipLaunchKernelGGL(nucleon_finish, dim3((Lt + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
+                       (int32_t)nchunks, t0, d_out);
+    QDP_CHECK(check_launch(ctx, "nucleon finish kernel"));
     double* host;
     QDP_CHECK(host_result_buffer(ctx, out_bytes, &host));
     QDP_HIP(ctx, hipMemcpyAsync(host, d_out, out_bytes, hipMemcpyDeviceToHost, ctx->stream));

@@ -171,6 +171,8 @@ qdp_status smear_jacobi_impl(Ctx* ctx, uint64_t gauge, const uint64_t* src, cons
 qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, double kappa,
                             int32_t n_iter);
 qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
+                                int32_t t0, int32_t j_decay, const int32_t* moms, int32_t nmom, double* out);
+qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd, int32_t kind, int32_t parity,
                                 int32_t t0, int32_t j_decay, double* out);
 qdp_status eval_impl(Ctx* ctx, const qdp_expr* expr, uint64_t dest, qdp_subset subset,
                      int32_t assign);

@@ -611,7 +611,7 @@ qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape) {
         const int sw = shape->site_waves, cg = shape->col_groups;
         if (sw < 1 || cg < 1 || cg > 12 || sw * cg > 4 || shape->xcd < 0 || shape->xcd > 1 ||
             !(shape->waves_per_simd == 0 || shape->waves_per_simd == 2 || shape->waves_per_simd == 3) ||
-            shape->flat < 0 || shape->flat > 1)
+            shape->flat < 0 || shape->flat > 1 || shape->reserved != 0)
             return set_error(ctx, QDP_ERR_ARG, "launch shape out of range (site_waves * col_groups <= 4)");
     }
     ctx->forced = *shape;
@@ -668,7 +668,26 @@ qdp_status qdp_hadron_contract(qdp_ctx* ctx, const qdp_field* S1, const qdp_fiel
     if (!ctx) return QDP_ERR_ARG;
     if (!S1 || !S2 || !out) return set_error(ctx, QDP_ERR_ARG, "null argument");
     QDP_API_BEGIN
-    return hadron_contract_impl(ctx, S1, S2, gamma_mask, t0, j_decay, out);
+    return hadron_contract_impl(ctx, S1, S2, gamma_mask, t0, j_decay, nullptr, 0, out);
+    QDP_API_END(ctx)
+}
+
+qdp_status qdp_hadron_contract_mom(qdp_ctx* ctx, const qdp_field* S1, const qdp_field* S2, uint32_t gamma_mask,
+                                   const int32_t* moms, int32_t nmom, int32_t t0, int32_t j_decay, double* out) {
+    if (!ctx) return QDP_ERR_ARG;
+    if (!S1 || !S2 || !out || !moms) return set_error(ctx, QDP_ERR_ARG, "null argument");
+    if (nmom < 1) return set_error(ctx, QDP_ERR_ARG, "contract_mom: nmom must be >= 1");
+    QDP_API_BEGIN
+    return hadron_contract_impl(ctx, S1, S2, gamma_mask, t0, j_decay, moms, nmom, out);
+    QDP_API_END(ctx)
+}
+
+qdp_status qdp_baryon_contract(qdp_ctx* ctx, const qdp_field* Su, const qdp_field* Sd, int32_t kind,
+                               int32_t parity, int32_t t0, int32_t j_decay, double* out) {
+    if (!ctx) return QDP_ERR_ARG;
+    if (!Su || !Sd || !out) return set_error(ctx, QDP_ERR_ARG, "null argument");
+    QDP_API_BEGIN
+    return baryon_contract_impl(ctx, Su, Sd, kind, parity, t0, j_decay, out);
     QDP_API_END(ctx)
 }
 

@@ -31,6 +31,7 @@ ASSIGN = {"=": 0, "+=": 1, "-=": 2, "*=": 3}
 SMEAR_FULL, SMEAR_EVEN_ODD = 0, 1
 INIT_NO_AUTOTUNE, INIT_NO_GRAPH = 1, 2
 RANDOM_SU3, RANDOM_GAUSSIAN = 0, 1
+BARYON_PROTON = 0
 OPS = {"field": 0, "gauge": 1, "real_const": 2, "complex_const": 3, "shift": 4, "neg": 5,
        "conj": 6, "adj": 7, "add": 8, "sub": 9, "mul": 10, "gamma_left": 11, "gamma_right": 12,
        "trace": 13, "trace_color": 14, "trace_spin": 15, "real": 16, "imag": 17,
@@ -111,6 +112,9 @@ SIGNATURES = {
     "qdp_smear_jacobi_to": (_i32, [_vp, _u64, _u64p, _u64p, _i32, _dbl, _i32, _i32, _i32]),
     "qdp_smear_jacobi_batch": (_i32, [_vp, _c.POINTER(qdp_smear_job), _i32, _dbl, _i32]),
     "qdp_hadron_contract": (_i32, [_vp, _u64p, _u64p, _u32, _i32, _i32, _dp]),
+    "qdp_hadron_contract_mom": (_i32, [_vp, _u64p, _u64p, _u32, _c.POINTER(_c.c_int32), _i32, _i32, _i32,
+                                       _dp]),
+    "qdp_baryon_contract": (_i32, [_vp, _u64p, _u64p, _i32, _i32, _i32, _i32, _dp]),
     "qdp_cache_stats": (_i32, [_vp, _c.POINTER(qdp_cache_stats_t)]),
     "qdp_cache_evict": (_i32, [_vp, _u64]),
     "qdp_cache_evict_all": (_i32, [_vp]),
@@ -336,6 +340,26 @@ class Context:
                                            out.ctypes.data_as(_dp)))
         return out.view(np.complex128).reshape(16, Lt)
 
+    def contract_mom(self, S1, S2, moms, mask=0xFFFF, t0=0, j_decay=3):
+        """C_n(p, t), shape (nmom, 16, Lt), for integer momenta `moms`."""
+        lat = self.field_meta[S1[0]][0]
+        Lt = self.lattice_dims[lat][3]
+        k = np.ascontiguousarray(np.asarray(moms, dtype=np.int32).reshape(-1, 3))
+        out = np.zeros(k.shape[0] * 16 * Lt * 2, dtype=np.float64)
+        self.check(lib.qdp_hadron_contract_mom(self.h, _u64_array(S1), _u64_array(S2), mask,
+                                               k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k.shape[0],
+                                               t0, j_decay, out.ctypes.data_as(_dp)))
+        return out.view(np.complex128).reshape(k.shape[0], 16, Lt)
+
+    def nucleon(self, Su, Sd, parity=1, t0=0, j_decay=3):
+        """Proton two-point function C(t), shape (Lt,) complex."""
+        lat = self.field_meta[Su[0]][0]
+        Lt = self.lattice_dims[lat][3]
+        out = np.zeros(Lt * 2, dtype=np.float64)
+        self.check(lib.qdp_baryon_contract(self.h, _u64_array(Su), _u64_array(Sd), BARYON_PROTON, parity, t0,
+                                           j_decay, out.ctypes.data_as(_dp)))
+        return out.view(np.complex128)
+
     def fill_random_su3(self, gauge, seed):
         self.check(lib.qdp_fill_random(self.h, gauge, RANDOM_SU3, seed, 0, 1.0))
 
@@ -384,6 +408,7 @@ class Context:
         self.check(lib.qdp_smear_set_shape(self.h, ctypes.byref(s)))
 
     def get_shape(self):
+        """(site_waves, col_groups, xcd, waves_per_simd, flat) of the last smearing call."""
         s = qdp_launch_shape()
         self.check(lib.qdp_smear_get_shape(self.h, ctypes.byref(s)))
         return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd, s.flat)

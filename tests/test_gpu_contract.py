@@ -126,3 +126,89 @@ def test_chain_source_sink_contraction(qdp, prec):
     assert corr_err(C, C_ref) <= TOL[prec]
     for f in [g] + s + p:
         qdp.free(f)
+
+
+MOMS = [(0, 0, 0), (1, 0, 0), (0, -1, 2), (2, 3, 1), (-1, -1, -1), (5, 0, 3)]
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16S"])
+@pytest.mark.parametrize("dims", [(4, 6, 2, 4), (12, 10, 6, 2)])
+def test_meson_momentum_projection(qdp, prec, dims):
+    """C_n(p, t) for six momenta (two launches of four, the second partly
+    empty) against the oracle on the stored inputs; slices of 48 and 720
+    sites (ragged 64-site chunks)."""
+    S1 = synth.gaussian_propagator(dims, 211)
+    S2 = synth.gaussian_propagator(dims, 212)
+    lat = qdp.lattice(dims)
+    a = upload_cols(qdp, lat, S1, prec)
+    b = upload_cols(qdp, lat, S2, prec)
+    S1r = np.stack([qdp.read(f) for f in a])
+    S2r = np.stack([qdp.read(f) for f in b])
+    ref = oracle.meson_mom(S1r, S2r, dims, MOMS)
+    got = qdp.contract_mom(a, b, MOMS)
+    assert got.shape == ref.shape
+    # FP64 products and sums on every storage precision; the plane wave
+    # carries about one ulp: only rounding order differs
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # p = 0 agrees with the zero-momentum call
+    c0 = qdp.contract(a, b)
+    assert np.max(np.abs(got[0] - c0)) <= 1e-13 * np.max(np.abs(c0))
+    # mask and time origin
+    part = qdp.contract_mom(a, b, MOMS[1:3], mask=1 << 15, t0=2)
+    assert np.count_nonzero(part[:, :15]) == 0
+    assert np.array_equal(part[:, 15], np.roll(got[1:3, 15], -2, axis=-1))
+    for f in a + b:
+        qdp.free(f)
+
+
+def test_meson_momentum_argument_errors(qdp):
+    from paper_1111_5596_amd.qdpmi import QdpError
+
+    dims = (4, 4, 4, 4)
+    lat = qdp.lattice(dims)
+    a = upload_cols(qdp, lat, synth.gaussian_propagator(dims, 3), "F32")
+    with pytest.raises(QdpError, match="ARG"):
+        qdp.contract_mom(a, a, np.zeros((0, 3), dtype=np.int32))
+    for f in a:
+        qdp.free(f)
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16S"])
+@pytest.mark.parametrize("dims", [(4, 6, 2, 4), (10, 6, 6, 2)])
+def test_nucleon_two_point(qdp, prec, dims):
+    """Proton correlator, both parities, distinct and equal u/d propagators,
+    against the oracle on the stored inputs (slices of 48 and 360 sites: one
+    partial block of 256)."""
+    Su = synth.gaussian_propagator(dims, 221)
+    Sd = synth.gaussian_propagator(dims, 222)
+    lat = qdp.lattice(dims)
+    u = upload_cols(qdp, lat, Su, prec)
+    d = upload_cols(qdp, lat, Sd, prec)
+    Sur = np.stack([qdp.read(f) for f in u])
+    Sdr = np.stack([qdp.read(f) for f in d])
+    for parity in (1, -1):
+        ref = oracle.nucleon(Sur, Sdr, dims, parity)
+        got = qdp.nucleon(u, d, parity=parity)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref)), parity
+    ref = oracle.nucleon(Sur, Sur, dims, 1)
+    got = qdp.nucleon(u, u, parity=1, t0=1)
+    assert np.max(np.abs(np.roll(got, 1) - ref)) <= 1e-11 * np.max(np.abs(ref))
+    assert np.array_equal(got, qdp.nucleon(u, u, parity=1, t0=1))  # repeatable bitwise
+    for f in u + d:
+        qdp.free(f)
+
+
+def test_nucleon_argument_errors(qdp):
+    from paper_1111_5596_amd import qdpmi
+
+    dims = (4, 4, 4, 4)
+    lat = qdp.lattice(dims)
+    u = upload_cols(qdp, lat, synth.gaussian_propagator(dims, 3), "F32")
+    with pytest.raises(qdpmi.QdpError, match="ARG"):
+        qdp.nucleon(u, u, parity=0)
+    out = np.zeros(8)
+    st = qdpmi.lib.qdp_baryon_contract(qdp.h, qdpmi._u64_array(u), qdpmi._u64_array(u), 7, 1, 0, 3,
+                                       out.ctypes.data_as(qdpmi._dp))
+    assert st == -6  # QDP_ERR_UNSUPPORTED
+    for f in u:
+        qdp.free(f)
