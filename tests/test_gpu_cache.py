@@ -64,11 +64,13 @@ def test_spill_and_fill_keep_results_bitwise():
 
 
 def test_explicit_evict_and_pool_limit():
+    from paper_1111_5596_amd.qdpmi import QdpError
+
     dims = (4, 4, 4, 4)
     q = _ctx(64 << 20, 16 << 20)
     try:
         lat = q.lattice(dims)
-        P = synth.gaussian_propagator(dims, 9, ncols=3)
+        P = synth.gaussian_propagator(dims, 9, ncols=4)
         fs = []
         for c in P:
             f = q.alloc(lat, "FERMION", "F64")
@@ -82,12 +84,21 @@ def test_explicit_evict_and_pool_limit():
         assert np.array_equal(q.read(fs[2]), P[1])
         q.evict_all()
         assert all(q.info(f).on_device == 0 for f in fs)
-        q.set_pool_limit(q.info(fs[0]).bytes * 2 + 4096)
-        st = q.cache_stats()
-        assert st["pool_limit"] <= q.info(fs[0]).bytes * 2 + 4096
-        # computing with all three needs more than the limit: LRU spills make room
-        q.eval([("field", fs[0]), ("field", fs[1]), ("add",)], fs[2])
+        nb = q.info(fs[0]).bytes
+        q.set_pool_limit(3 * nb + 4096)  # room for three of the four fields
+        assert q.cache_stats()["pool_limit"] <= 3 * nb + 4096
+        q.eval([("field", fs[0]), ("field", fs[1]), ("add",)], fs[2])  # three operands fit
+        spills = q.cache_stats()["spills"]
+        # a fourth field on the device forces the least recently used one out
+        q.eval([("field", fs[0]), ("field", fs[1]), ("sub",)], fs[3])
+        assert q.cache_stats()["spills"] == spills + 1 and q.info(fs[2]).on_device == 0
         assert np.allclose(q.read(fs[2]), P[0] + P[1], rtol=0, atol=1e-15)
+        assert np.allclose(q.read(fs[3]), P[0] - P[1], rtol=0, atol=1e-15)
+        # one expression over four fields cannot fit: NOMEM, destination untouched
+        before = q.read(fs[3])
+        with pytest.raises(QdpError, match="NOMEM"):
+            q.eval([("field", fs[0]), ("field", fs[1]), ("add",), ("field", fs[2]), ("add",)], fs[3])
+        assert np.array_equal(q.read(fs[3]), before)
     finally:
         q.close()
 
@@ -95,11 +106,11 @@ def test_explicit_evict_and_pool_limit():
 def test_nomem_and_fault_injection_leave_no_state():
     from paper_1111_5596_amd.qdpmi import QdpError
 
-    dims = (4, 4, 4, 4)
+    dims = (8, 8, 8, 8)
     q = _ctx(4 << 20, 0)
     try:
         lat = q.lattice(dims)
-        f = q.alloc(lat, "FERMION", "F64")
+        f = q.alloc(lat, "FERMION", "F64")  # 0.8 MB
         before = q.cache_stats()
         with pytest.raises(QdpError, match="NOMEM"):
             q.alloc(lat, "PROPAGATOR", "F64")  # 9.4 MB > pool, no spill area
@@ -127,7 +138,7 @@ def test_pool_malloc_spills_fields_and_stays_put():
     dims = (8, 8, 8, 8)
     V = synth.volume(dims)
     col_bytes = 192 * V  # FP64 FERMION
-    q = _ctx(8 * col_bytes + (1 << 20), 64 << 20)
+    q = _ctx(8 * col_bytes + 4096, 64 << 20)  # six fields + the 3-column block do not fit
     try:
         lat = q.lattice(dims)
         P = synth.gaussian_propagator(dims, 31, ncols=6)
