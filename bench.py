@@ -177,6 +177,33 @@ def run_batch64(q, torch):
     return su, dt
 
 
+def run_hadron_extras(q, torch, lat, V):
+    """Wall time of the other hadron contractions on the same 48^3x96 F16S
+    propagator (12 Gaussian columns): zero-momentum mesons, mesons at the
+    four momenta (0,0,0), (1,0,0), (0,1,0), (0,0,1) in one launch, and the
+    proton two-point function.  Each call synchronises; the median of 3."""
+    cols = [q.alloc(lat, "FERMION", "F16S") for _ in range(12)]
+    for j, f in enumerate(cols):
+        q.fill_gaussian(f, 105, j, (24.0 * V) ** -0.5)
+    moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    calls = {"meson_p0_ms": lambda: q.contract(cols, cols),
+             "meson_4mom_ms": lambda: q.contract_mom(cols, cols, moms),
+             "nucleon_ms": lambda: q.nucleon(cols, cols)}
+    out = {}
+    for name, fn in calls.items():
+        fn()
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        out[name] = sorted(ts)[1]
+    for f in cols:
+        q.free(f)
+    return out
+
+
 def copy_bandwidth(q, torch, lat):
     """Device copy of one F32 fermion field (qdp_eval dest = src): the plain
     copy kernel used to scale the HBM counters and as the attainable
@@ -214,15 +241,22 @@ def measured_traffic():
     """HBM bytes per launch of the profiled kernel (rocprofv3 FETCH_SIZE +
     WRITE_SIZE, scaled by the copy-kernel calibration), if the committed
     measurement was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "smear_f16s_48c96_traffic.json")
+    path = os.path.join(ROOT, "profiles", "smear_f16s_48c96_traffic.txt")
+    rec = {}
     try:
         with open(path) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    rec[k.strip()] = v.strip()
+    except OSError:
         return None
     if rec.get("kernel_source_sha256") != kernel_source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(full_steps_niter=NITER):
@@ -292,6 +326,8 @@ def main():
     if not args.no_batch:
         batch = run_batch64(q, torch)
         print(f"[bench] 64-lattice batch {batch[1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    hadron = run_hadron_extras(q, torch, lat, V)
+    print(f"[bench] hadron contractions {hadron}", file=sys.stderr, flush=True)
     plain = None
     if not args.no_plain:
         plain = run_plain(q, torch, lat, V)
@@ -344,6 +380,7 @@ def main():
         "value": site_updates / (full["ms_per_step"] * 1e-3), "ms_per_step": full["ms_per_step"],
         "smear_GBps_model": MODEL_BYTES_PER_SITE_UPDATE[("F16S", False)] * 12 * V / (full["smear_ms"] / NITER * 1e-3) / 1e9,
         "launch_shape": list(full["shape"])}
+    out["hadron_contractions_48c96_f16s"] = hadron
     if batch:
         out["batch64_fp32"] = {"value": batch[0] / batch[1], "site_updates": batch[0], "ms": batch[1] * 1e3,
                                "workload": "64 lattices from {8^3x16,12^3x24,16^3x32,24^3x48}, 12 columns, "

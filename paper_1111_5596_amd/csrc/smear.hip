@@ -382,10 +382,11 @@ std::vector<void*> arg_pointers(Launch& L) {
     return p;
 }
 
-// Launch a sequence of kernels; consecutive groups of `width` launches are
-// independent of each other and each group depends on the whole previous
-// group (width 2: the even and odd passes of one smearing iteration).
-qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph, int width = 1) {
+// Launch a sequence of kernels in order (from a cached HIP graph when
+// use_graph).  Each launch depends on the one before it: the two subset
+// passes of an iteration could run concurrently, but measured that way they
+// are no faster and each one's duration stops being observable.
+qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
     if (ls.empty()) return QDP_OK;
     if (!use_graph || ls.size() < 2) {
         for (auto& L : ls) {
@@ -395,7 +396,7 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph, int w
         return QDP_OK;
     }
     // Graph cache keyed by every launch's function, shape and argument bytes.
-    std::string key(reinterpret_cast<const char*>(&width), sizeof width);
+    std::string key;
     for (auto& L : ls) {
         key.append(reinterpret_cast<const char*>(&L.func), sizeof(L.func));
         key.append(reinterpret_cast<const char*>(&L.grid), sizeof(L.grid));
@@ -413,7 +414,7 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph, int w
         }
         hipGraph_t graph;
         QDP_HIP(ctx, hipGraphCreate(&graph, 0));
-        std::vector<hipGraphNode_t> prev, cur;
+        hipGraphNode_t prev = nullptr;
         for (size_t i = 0; i < ls.size(); ++i) {
             Launch& L = ls[i];
             auto p = arg_pointers(L);
@@ -425,16 +426,12 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph, int w
             np.kernelParams = p.data();
             np.extra = nullptr;
             hipGraphNode_t node;
-            hipError_t e = hipGraphAddKernelNode(&node, graph, prev.empty() ? nullptr : prev.data(), prev.size(), &np);
+            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
             if (e != hipSuccess) {
                 hipGraphDestroy(graph);
                 return hip_error(ctx, e, "hipGraphAddKernelNode");
             }
-            cur.push_back(node);
-            if ((int)cur.size() == width || i + 1 == ls.size()) {
-                prev.swap(cur);
-                cur.clear();
-            }
+            prev = node;
         }
         hipGraphExec_t exec;
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -598,18 +595,19 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
                 if (sw * cg > 4 || cg > job.ncols) continue;
                 for (int xcd : {0, 1})
                     for (int occ : {0, 2, 3}) {
-                    if (prec == QDP_F64 && occ) continue;
-                    qdp_launch_shape sh{sw, cg, xcd, occ, flat, 0};
-                    float ms;
-                    QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));
-                    if (log)
-                        std::fprintf(stderr, "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d: %.4f ms\n",
-                                     prec, job.ncols, (long long)count, sw, cg, xcd, occ, flat, ms);
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = sh;
+                        if (prec == QDP_F64 && occ) continue;
+                        qdp_launch_shape sh{sw, cg, xcd, occ, flat, 0};
+                        float ms;
+                        QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));
+                        if (log)
+                            std::fprintf(stderr,
+                                         "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d: %.4f ms\n",
+                                         prec, job.ncols, (long long)count, sw, cg, xcd, occ, flat, ms);
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = sh;
+                        }
                     }
-                }
             }
     }
     ctx->tuned[key] = best;
@@ -713,7 +711,7 @@ qdp_status smear_jacobi_impl(Ctx* ctx, uint64_t gauge, const uint64_t* src, cons
             const SmearJob& job = k == 1 ? first : (k % 2 == 0 ? to_dst : to_tmp);
             for (const Pass& p : passes) ls.push_back(make_single_launch(prec, job, p.begin, p.count, sh, kappa));
         }
-        QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH), (int)passes.size()));
+        QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH)));
         QDP_CHECK(check_launch(ctx, "smear kernel"));
     }
     if (n_iter % 2 == 1) {

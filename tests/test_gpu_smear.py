@@ -117,12 +117,12 @@ def test_launch_shapes_bitwise(qdp, prec):
     out = qdp.alloc(lat, "FERMION", prec)
     ref = None
     try:
-        for sw, cg, xcd, occ, flat in [(1, 1, 0, 0, 0), (4, 1, 1, 2, 0), (2, 2, 1, 3, 0), (1, 3, 0, 2, 1),
-                                       (1, 4, 1, 0, 1), (2, 1, 0, 3, 1), (4, 1, 1, 2, 1)]:
-            qdp.set_shape(sw, cg, xcd, occ, flat)
+        for shape in [(1, 1, 0, 0, 0), (4, 1, 1, 2, 0), (2, 2, 1, 3, 0), (1, 3, 0, 2, 1),
+                      (1, 4, 1, 0, 1), (2, 1, 0, 3, 1), (4, 1, 1, 2, 1)]:
+            qdp.set_shape(*shape)
             outs = [qdp.alloc(lat, "FERMION", prec) for _ in fs]
             qdp.smear_to(g, fs, outs, 0.25, 5, mode=1)
-            assert qdp.get_shape() == (sw, cg, xcd, occ, flat)
+            assert qdp.get_shape() == shape
             vals = [qdp.read(o) for o in outs]
             if ref is None:
                 ref = vals
