@@ -154,15 +154,19 @@ struct FieldRef {
     __device__ __forceinline__ explicit FieldRef(const char* p) : base(p) {
         if constexpr (BUF) rsrc = buffer_rsrc(p);
     }
+    // the row offset goes in the scalar offset operand (it is the same for
+    // every lane): as part of the per-lane offset it would cost a vector add
+    // per load, since the compiler cannot prove that sum free of wrap-around
+    // and so will not fold it into the instruction's immediate offset
     __device__ __forceinline__ T load(int row, int64_t so) const {
         if constexpr (BUF)
-            return bload<T>(rsrc, (uint32_t)so + (uint32_t)(row * 64 * (int)sizeof(T)), 0u);
+            return bload<T>(rsrc, (uint32_t)so, (uint32_t)(row * 64 * (int)sizeof(T)));
         else
             return *reinterpret_cast<const T*>(base + so + (int64_t)row * 64 * (int64_t)sizeof(T));
     }
     __device__ __forceinline__ void store(T v, int row, int64_t so) const {
         if constexpr (BUF)
-            bstore(v, rsrc, (uint32_t)so + (uint32_t)(row * 64 * (int)sizeof(T)), 0u);
+            bstore(v, rsrc, (uint32_t)so, (uint32_t)(row * 64 * (int)sizeof(T)));
         else
             *reinterpret_cast<T*>(const_cast<char*>(base) + so + (int64_t)row * 64 * (int64_t)sizeof(T)) = v;
     }
