@@ -295,6 +295,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice batch workload")
+    ap.add_argument("--shape", default=None,
+                    help="force the smearing launch shape site_waves,col_groups,xcd,waves_per_simd,flat "
+                         "instead of autotuning (for profiler runs that must repeat a measured shape)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -308,6 +311,8 @@ def main():
 
     V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
     q = qdpmi.Context(pool_bytes=72 << 30)
+    if args.shape:
+        q.set_shape(*[int(x) for x in args.shape.split(",")])
     lat = q.lattice(DIMS)
     site_updates = 12 * V * NITER
     launches = 2 * NITER
