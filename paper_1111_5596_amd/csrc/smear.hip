@@ -772,15 +772,19 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
             QDP_CHECK(field_create(ctx, lats[j], QDP_FERMION, prec, &tmp[j][c]));
     }
 
-    qdp_launch_shape sh = ctx->forced.site_waves > 0 ? ctx->forced : default_shape();
-    for (int32_t j = 0; j < njobs; ++j)
-        if (needs_flat(ctx, jobs[j].gauge, lats[j], prec)) sh.flat = 1;
-    ctx->last_shape = sh;
-    const int64_t tile_sites = 64LL * sh.site_waves;
+    int flat = 0;
+    std::string tune_key(reinterpret_cast<const char*>(&prec), sizeof prec);
+    for (int32_t j = 0; j < njobs; ++j) {
+        if (needs_flat(ctx, jobs[j].gauge, lats[j], prec)) flat = 1;
+        const Geometry& g = find_lattice(ctx, lats[j])->geo;
+        tune_key.append(reinterpret_cast<const char*>(g.L), sizeof g.L);
+        tune_key.append(reinterpret_cast<const char*>(&jobs[j].ncols), sizeof(int32_t));
+    }
 
+    // work lists for the tile sizes 64 * site_waves, site_waves = 1..4
     PinSet pins(ctx);
     std::vector<SmearJob> h_first(njobs), h_dst(njobs), h_tmp(njobs);
-    std::vector<int64_t> h_tiles(njobs + 1, 0);
+    std::vector<int64_t> h_tiles(4 * (njobs + 1), 0);
     for (int32_t j = 0; j < njobs; ++j) {
         const Geometry& g = find_lattice(ctx, lats[j])->geo;
         char* pg;
@@ -805,10 +809,13 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
         h_first[j] = a;
         h_dst[j] = b;
         h_tmp[j] = c;
-        h_tiles[j + 1] = h_tiles[j] + (g.V + tile_sites - 1) / tile_sites;
+        for (int k = 0; k < 4; ++k) {
+            const int64_t tile_sites = 64LL * (k + 1);
+            h_tiles[k * (njobs + 1) + j + 1] = h_tiles[k * (njobs + 1) + j] + (g.V + tile_sites - 1) / tile_sites;
+        }
     }
     const size_t jb = sizeof(SmearJob) * njobs;
-    const size_t tb = sizeof(int64_t) * (njobs + 1);
+    const size_t tb = sizeof(int64_t) * 4 * (njobs + 1);
     PoolTemp dev;
     QDP_CHECK(dev.alloc(ctx, (int64_t)(3 * jb + tb + 1024)));
     char* d_first = dev.ptr();
@@ -820,25 +827,85 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
     QDP_HIP(ctx, hipMemcpyAsync(d_tmp, h_tmp.data(), jb, hipMemcpyHostToDevice, ctx->stream));
     QDP_HIP(ctx, hipMemcpyAsync(d_tiles, h_tiles.data(), tb, hipMemcpyHostToDevice, ctx->stream));
 
-    SmearLaunch ln{};
-    ln.site_waves = sh.site_waves;
-    ln.col_groups = sh.col_groups;
-    ln.xcd = sh.xcd;
-    ln.kappa = kappa;
-    const int64_t ntiles = h_tiles[njobs];
-    int64_t grid = std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * 8);
-    grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
-    std::vector<Launch> ls;
-    for (int32_t k = 1; k <= n_iter; ++k) {
-        const SmearJob* J = reinterpret_cast<const SmearJob*>(k == 1 ? d_first : (k % 2 == 0 ? d_dst : d_tmp));
-        const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles);
+    // one persistent launch over every lattice's tiles with job list J
+    auto batch_launch = [&](const char* J, const qdp_launch_shape& sh) {
+        const int k = sh.site_waves - 1;  // 1..4, checked by qdp_smear_set_shape
+        SmearLaunch ln{};
+        ln.site_waves = sh.site_waves;
+        ln.col_groups = sh.col_groups;
+        ln.xcd = sh.xcd;
+        ln.kappa = kappa;
+        const int64_t ntiles = h_tiles[k * (njobs + 1) + njobs];
+        int64_t grid = std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * 8);
+        grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
+        const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles) + k * (njobs + 1);
         Launch L;
         L.func = smear_func(prec, sh, true);
         L.grid = dim3((unsigned)grid);
         L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
-        pack_args(L, J, T, njobs, ln);
-        ls.push_back(std::move(L));
+        pack_args(L, reinterpret_cast<const SmearJob*>(J), T, njobs, ln);
+        return L;
+    };
+
+    qdp_launch_shape sh;
+    if (ctx->forced.site_waves > 0) {
+        sh = ctx->forced;
+        sh.flat |= flat;
+    } else if (ctx->tuned_batch.count(tune_key)) {
+        sh = ctx->tuned_batch[tune_key];
+    } else {
+        // time one launch per candidate shape (the first iteration's job list:
+        // it writes only the temporaries, which the real iterations overwrite)
+        sh = default_shape();
+        sh.flat = flat;
+        const bool log = std::getenv("QDP_AUTOTUNE_LOG") != nullptr;
+        if (!(ctx->flags & QDP_INIT_NO_AUTOTUNE)) {
+            float best_ms = 1e30f;
+            hipEvent_t e0, e1;
+            QDP_HIP(ctx, hipEventCreate(&e0));
+            QDP_HIP(ctx, hipEventCreate(&e1));
+            const int groups[] = {1, 2, 3, 4, 6};
+            for (int sw : {1, 2, 4})
+                for (int cg : groups)
+                    for (int xcd : {0, 1})
+                        for (int occ : {0, 2, 3}) {
+                            if (sw * cg > 4 || (prec == QDP_F64 && occ)) continue;
+                            const qdp_launch_shape cand{sw, cg, xcd, occ, flat, 0};
+                            Launch L = batch_launch(d_first, cand);
+                            auto p = arg_pointers(L);
+                            float best = 1e30f;
+                            for (int rep = 0; rep < 2; ++rep) {
+                                hipEventRecord(e0, ctx->stream);
+                                hipLaunchKernel(L.func, L.grid, L.block, p.data(), 0, ctx->stream);
+                                hipEventRecord(e1, ctx->stream);
+                                hipError_t err = hipEventSynchronize(e1);
+                                if (err != hipSuccess) {
+                                    hipEventDestroy(e0);
+                                    hipEventDestroy(e1);
+                                    return hip_error(ctx, err, "batch autotune launch");
+                                }
+                                float t = 0.f;
+                                hipEventElapsedTime(&t, e0, e1);
+                                if (rep > 0) best = std::min(best, t);
+                            }
+                            if (log)
+                                std::fprintf(stderr, "[qdpmi autotune] batch of %d prec %d shape %d %d %d %d %d: %.4f ms\n",
+                                             njobs, prec, sw, cg, xcd, occ, flat, best);
+                            if (best < best_ms) {
+                                best_ms = best;
+                                sh = cand;
+                            }
+                        }
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+        }
+        ctx->tuned_batch[tune_key] = sh;
     }
+    ctx->last_shape = sh;
+
+    std::vector<Launch> ls;
+    for (int32_t k = 1; k <= n_iter; ++k)
+        ls.push_back(batch_launch(k == 1 ? d_first : (k % 2 == 0 ? d_dst : d_tmp), sh));
     QDP_CHECK(run_launches(ctx, ls, !(ctx->flags & QDP_INIT_NO_GRAPH)));
     QDP_CHECK(check_launch(ctx, "smear batch kernel"));
     if (n_iter % 2 == 1) {
