@@ -227,12 +227,18 @@ def copy_bandwidth(q, torch, lat):
 
 
 def kernel_source_digest() -> str:
-    """Hash of the sources of the profiled smearing kernel."""
+    """Hash of the device code of the profiled smearing kernel: the kernel
+    part of smear.hip (everything before its host driver) and the device
+    headers it includes."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in ("smear.hip", "device.hpp", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_1111_5596_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_1111_5596_amd", "csrc")
+    with open(os.path.join(csrc, "smear.hip"), "rb") as f:
+        text = f.read()
+    h.update(text[:text.index(b"// Host driver")])
+    for name in ("device.hpp", "common.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
