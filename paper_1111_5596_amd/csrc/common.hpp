@@ -100,11 +100,29 @@ QDP_HD inline int64_t tile_site_offset(int64_t tb, int64_t esize, int64_t site) 
     return (site >> 6) * tb + (site & 63) * esize;
 }
 
+// Inside a tile the components are stored in rows of 16-byte chunks: row q
+// holds, for each of the 64 sites in turn, the q-th run of 16 / element-size
+// consecutive components of the site (4 F16S, 2 F32 or 1 F64 complex
+// numbers), so a lane fetches a chunk with one 16-byte load and a wavefront's
+// load covers 1024 contiguous bytes.  Fields whose per-site component count
+// is not a multiple of the chunk size (colour matrices, vectors and scalars
+// in F16S/F32) keep one row per component instead.
+QDP_HD inline int32_t chunk_elems(int32_t prec) { return (int32_t)(16 / prec_complex_bytes(prec)); }
+QDP_HD inline bool chunked_layout(int32_t nrec, int32_t ncomp, int32_t prec) {
+    return ((int64_t)nrec * ncomp) % chunk_elems(prec) == 0;
+}
+
 // Byte offset of component k of record rec at `site`.
 QDP_HD inline int64_t comp_offset(int32_t nrec, int32_t ncomp, int32_t prec, int32_t rec, int32_t comp,
                                   int64_t site) {
     const int64_t es = prec_complex_bytes(prec);
-    return tile_site_offset(tile_bytes(nrec, ncomp, prec), es, site) + ((int64_t)rec * ncomp + comp) * 64 * es;
+    const int64_t tb = tile_bytes(nrec, ncomp, prec);
+    const int64_t e = (int64_t)rec * ncomp + comp;
+    if (chunked_layout(nrec, ncomp, prec)) {
+        const int64_t ce = chunk_elems(prec);
+        return tile_site_offset(tb, 16, site) + (e / ce) * 64 * 16 + (e % ce) * es;
+    }
+    return tile_site_offset(tb, es, site) + e * 64 * es;
 }
 
 // Byte offset of the F16S scale of record rec at `site`.

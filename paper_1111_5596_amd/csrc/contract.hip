@@ -90,21 +90,18 @@ struct RawCol<QDP_F16S> {
     }
 };
 
+// One column at one site: 16-byte chunk loads (3 for F16S, 6 for F32, 12 for
+// F64) and, for F16S, the record scale.
 template <int PREC, bool BUF>
 __device__ __forceinline__ void load_column(const char* base, int32_t s, RawCol<PREC>& r) {
+    const int64_t tb = tile_bytes(1, 12, PREC);
+    const ChunkRef<BUF> f(base);
+    const int64_t so16 = tile_site_offset(tb, 16, s);
     if constexpr (PREC == QDP_F16S) {
-        const FieldRef<half2_t, BUF> f(base);
-        const FieldRef<float, BUF> sc(base);
-        const int64_t so = site_off<half2_t>(s, tile_bytes(1, 12, QDP_F16S));
-        r.scale = sc.load(12, so);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) r.h[k] = f.load(k, so);
+        r.scale = FieldRef<float, BUF>(base).load(12, site_off<float>(s, tb));
+        load_elems<0, 12>(f, so16, r.h);
     } else {
-        using T = typename std::remove_reference<decltype(r.v[0])>::type;
-        const FieldRef<T, BUF> f(base);
-        const int64_t so = site_off<T>(s, tile_bytes(1, 12, PREC));
-#pragma unroll
-        for (int k = 0; k < 12; ++k) r.v[k] = f.load(k, so);
+        load_elems<0, 12>(f, so16, r.v);
     }
 }
 
@@ -301,28 +298,31 @@ __device__ __forceinline__ double2 times_ik(double2 z, int k) {
 }
 
 // X[r][r'] = component (r, a) of column 3 r' + ap at checkerboard site s.
+// Component 3 r + a lies in chunk (3 r + a) / CE at position (3 r + a) % CE;
+// with a known only at run time each component is one element-sized load.
 template <int PREC, bool BUF>
 __device__ __forceinline__ void load_block(const char* const* cols, int a, int ap, int32_t s, double2 X[4][4]) {
+    using T = typename std::conditional<PREC == QDP_F64, double2,
+                                        typename std::conditional<PREC == QDP_F32, float2, half2_t>::type>::type;
+    constexpr int CE = 16 / sizeof(T);
+    const int64_t tb = tile_bytes(1, 12, PREC);
+    const int64_t so16 = tile_site_offset(tb, 16, s);
 #pragma unroll
     for (int rp = 0; rp < 4; ++rp) {
         const char* base = cols[3 * rp + ap];
-        if constexpr (PREC == QDP_F16S) {
-            const FieldRef<half2_t, BUF> f(base);
-            const FieldRef<float, BUF> sc(base);
-            const int64_t so = site_off<half2_t>(s, tile_bytes(1, 12, QDP_F16S));
-            const float scale = sc.load(12, so);
+        const FieldRef<T, BUF> f(base);
+        float scale = 1.f;
+        if constexpr (PREC == QDP_F16S) scale = FieldRef<float, BUF>(base).load(12, site_off<float>(s, tb));
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float2 v = f16s_decode(f.load(3 * r + a, so), scale);
-                X[r][rp] = make_double2(v.x, v.y);
-            }
-        } else {
-            using T = typename std::conditional<PREC == QDP_F64, double2, float2>::type;
-            const FieldRef<T, BUF> f(base);
-            const int64_t so = site_off<T>(s, tile_bytes(1, 12, PREC));
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const T v = f.load(3 * r + a, so);
+        for (int r = 0; r < 4; ++r) {
+            const int e = 3 * r + a;
+            // FieldRef rows are 64 elements apart; a chunk row is 64 * 16 bytes
+            const int64_t off = so16 + (int64_t)(e % CE) * (int64_t)sizeof(T);
+            const T v = f.load((e / CE) * CE, off);
+            if constexpr (PREC == QDP_F16S) {
+                const float2 d = f16s_decode(v, scale);
+                X[r][rp] = make_double2(d.x, d.y);
+            } else {
                 X[r][rp] = make_double2(v.x, v.y);
             }
         }

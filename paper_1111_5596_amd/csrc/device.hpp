@@ -172,6 +172,65 @@ struct FieldRef {
     }
 };
 
+// Access to the 16-byte chunks of a chunked field (see common.hpp): `so16` is
+// tile_site_offset(tile bytes, 16, site); chunk q of that site is q * 1024
+// bytes further.  Same addressing choices as FieldRef.
+template <bool BUF>
+struct ChunkRef {
+    const char* base;
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ explicit ChunkRef(const char* p) : base(p) {
+        if constexpr (BUF) rsrc = buffer_rsrc(p);
+    }
+    __device__ __forceinline__ u32x4_t load(int q, int64_t so16) const {
+        if constexpr (BUF)
+            return __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(uint32_t)so16, q * 1024, 0);
+        else
+            return *reinterpret_cast<const u32x4_t*>(base + so16 + (int64_t)q * 1024);
+    }
+    __device__ __forceinline__ void store(u32x4_t v, int q, int64_t so16) const {
+        if constexpr (BUF)
+            __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, (int)(uint32_t)so16, q * 1024, 0);
+        else
+            *reinterpret_cast<u32x4_t*>(const_cast<char*>(base) + so16 + (int64_t)q * 1024) = v;
+    }
+};
+
+template <typename T2>
+struct Chunk {
+    T2 v[16 / sizeof(T2)];
+};
+
+// Complex elements [E0, E0 + N) of a site of a chunked field (element e lies
+// in chunk e / (16 / sizeof(T2))), one 16-byte load per chunk touched.
+template <int E0, int N, typename T2, bool BUF>
+__device__ __forceinline__ void load_elems(const ChunkRef<BUF>& f, int64_t so16, T2* out) {
+    constexpr int CE = 16 / sizeof(T2);
+#pragma unroll
+    for (int q = E0 / CE; q <= (E0 + N - 1) / CE; ++q) {
+        const Chunk<T2> c = __builtin_bit_cast(Chunk<T2>, f.load(q, so16));
+#pragma unroll
+        for (int j = 0; j < CE; ++j) {
+            const int e = q * CE + j;
+            if (e >= E0 && e < E0 + N) out[e - E0] = c.v[j];
+        }
+    }
+}
+
+// Store elements [0, N) of a site, N a multiple of the chunk size.
+template <int N, typename T2, bool BUF>
+__device__ __forceinline__ void store_elems(const ChunkRef<BUF>& f, int64_t so16, const T2* in) {
+    constexpr int CE = 16 / sizeof(T2);
+    static_assert(N % CE == 0, "whole chunks only");
+#pragma unroll
+    for (int q = 0; q < N / CE; ++q) {
+        Chunk<T2> c;
+#pragma unroll
+        for (int j = 0; j < CE; ++j) c.v[j] = in[q * CE + j];
+        f.store(__builtin_bit_cast(u32x4_t, c), q, so16);
+    }
+}
+
 // Site offset in row 0 for elements of type T in tiles of `tb` bytes.
 template <typename T>
 __device__ __forceinline__ int64_t site_off(int32_t site, int64_t tb) {

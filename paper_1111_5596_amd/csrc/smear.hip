@@ -69,29 +69,34 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
     const SpatialNeighbours nb = spatial_neighbours(job.g, s);
     constexpr int PREC = sizeof(R) == 8 ? QDP_F64 : QDP_F32;
     const int64_t tbu = tile_bytes(4, 9, PREC), tbc = tile_bytes(1, 12, PREC);
-    const FieldRef<T2, BUF> U(job.gauge);
-    // site offsets: links at x and x - i, column values at x, x + i, x - i
-    const int64_t us = site_off<T2>(s, tbu);
-    const int64_t cs = site_off<T2>(s, tbc);
+    const ChunkRef<BUF> U(job.gauge);
+    // 16-byte-chunk site offsets: links at x and x - i, column values at x, x + i, x - i
+    const int64_t us = tile_site_offset(tbu, 16, s);
+    const int64_t cs = tile_site_offset(tbc, 16, s);
     int64_t ub_off[3], cf[3], cb[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        ub_off[i] = site_off<T2>(nb.bwd[i], tbu);
-        cf[i] = site_off<T2>(nb.fwd[i], tbc);
-        cb[i] = site_off<T2>(nb.bwd[i], tbc);
+        ub_off[i] = tile_site_offset(tbu, 16, nb.bwd[i]);
+        cf[i] = tile_site_offset(tbc, 16, nb.fwd[i]);
+        cb[i] = tile_site_offset(tbc, 16, nb.bwd[i]);
     }
 
+    // links: elements 9 i .. 9 i + 8 of the gauge record are U_i
     T2 uf[3][9], ub[3][9];
+    {
+        T2 u[27];
+        load_elems<0, 27>(U, us, u);
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            uf[i][k] = U.load(i * 9 + k, us);
-            ub[i][k] = U.load(i * 9 + k, ub_off[i]);
-        }
+            for (int k = 0; k < 9; ++k) uf[i][k] = u[9 * i + k];
+    }
+    load_elems<0, 9>(U, ub_off[0], ub[0]);
+    load_elems<9, 9>(U, ub_off[1], ub[1]);
+    load_elems<18, 9>(U, ub_off[2], ub[2]);
 
     for (int c = c0; c < c1; ++c) {
-        const FieldRef<T2, BUF> src(job.src[c]);
+        const ChunkRef<BUF> src(job.src[c]);
         T2 acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = T2{0, 0};
@@ -101,9 +106,7 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
         // the links stay in registers.
         T2 v[3][12];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int k = 0; k < 12; ++k) v[i][k] = src.load(k, cf[i]);
+        for (int i = 0; i < 3; ++i) load_elems<0, 12>(src, cf[i], v[i]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -115,11 +118,8 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
                     for (int b = 0; b < 3; ++b) cmac(acc[3 * sp + a], uf[i][3 * a + b], v[i][3 * sp + b]);
         T2 own[12];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int k = 0; k < 12; ++k) v[i][k] = src.load(k, cb[i]);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) own[k] = src.load(k, cs);
+        for (int i = 0; i < 3; ++i) load_elems<0, 12>(src, cb[i], v[i]);
+        load_elems<0, 12>(src, cs, own);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -129,14 +129,14 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
                     for (int b = 0; b < 3; ++b) cmac_conj(acc[3 * sp + a], ub[i][3 * b + a], v[i][3 * sp + b]);
-        const FieldRef<T2, BUF> dst(job.dst[c]);
+        T2 out[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            T2 o = own[k];
-            o.x = fmadd(kappa, acc[k].x, o.x);
-            o.y = fmadd(kappa, acc[k].y, o.y);
-            dst.store(o, k, cs);
+            out[k] = own[k];
+            out[k].x = fmadd(kappa, acc[k].x, out[k].x);
+            out[k].y = fmadd(kappa, acc[k].y, out[k].y);
         }
+        store_elems<12>(ChunkRef<BUF>(job.dst[c]), cs, out);
     }
 }
 
@@ -151,62 +151,68 @@ __device__ __forceinline__ float dot2(half2_t a, half2_t b, float c) {
 template <bool BUF>
 __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s, int c0, int c1,
                                                  float kappa) {
-    // half2 rows and FP32 scale rows have the same 4-byte elements, so the
-    // scale row of gauge record i is row 36 + i, of a column row 12
+    // data: 16-byte chunks (4 half2 each); F16S scales: rows of FP32 after the
+    // data, one per record (row 36 + i of the gauge tile, row 12 of a column
+    // tile, counted in 4-byte rows)
     const SpatialNeighbours nb = spatial_neighbours(job.g, s);
     const int64_t tbu = tile_bytes(4, 9, QDP_F16S), tbc = tile_bytes(1, 12, QDP_F16S);
-    const FieldRef<half2_t, BUF> U(job.gauge);
+    const ChunkRef<BUF> U(job.gauge);
     const FieldRef<float, BUF> Us(job.gauge);
-    const int64_t us = site_off<half2_t>(s, tbu);
-    const int64_t cs = site_off<half2_t>(s, tbc);
-    int64_t ub_off[3], cf[3], cb[3];
+    const int64_t us = tile_site_offset(tbu, 16, s), us4 = site_off<float>(s, tbu);
+    const int64_t cs = tile_site_offset(tbc, 16, s), cs4 = site_off<float>(s, tbc);
+    int64_t ub_off[3], ub4[3], cf[3], cf4[3], cb[3], cb4[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        ub_off[i] = site_off<half2_t>(nb.bwd[i], tbu);
-        cf[i] = site_off<half2_t>(nb.fwd[i], tbc);
-        cb[i] = site_off<half2_t>(nb.bwd[i], tbc);
+        ub_off[i] = tile_site_offset(tbu, 16, nb.bwd[i]);
+        ub4[i] = site_off<float>(nb.bwd[i], tbu);
+        cf[i] = tile_site_offset(tbc, 16, nb.fwd[i]);
+        cf4[i] = site_off<float>(nb.fwd[i], tbc);
+        cb[i] = tile_site_offset(tbc, 16, nb.bwd[i]);
+        cb4[i] = site_off<float>(nb.bwd[i], tbc);
     }
 
     // forward link u: re(u v) = (u.x, -u.y).v   im(u v) = (u.y, u.x).v
     // backward link w: re(w* v) = (w.x, w.y).v  im(w* v) = (-w.y, w.x).v
     half2_t fre[3][9], fim[3][9], bre[3][9], bim[3][9];
     float sf[3], sb[3];
+    {
+        half2_t u[27], w[3][9];
+        load_elems<0, 27>(U, us, u);
+        load_elems<0, 9>(U, ub_off[0], w[0]);
+        load_elems<9, 9>(U, ub_off[1], w[1]);
+        load_elems<18, 9>(U, ub_off[2], w[2]);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        sf[i] = Us.load(36 + i, us);
-        sb[i] = Us.load(36 + i, ub_off[i]);
+        for (int i = 0; i < 3; ++i) {
+            sf[i] = Us.load(36 + i, us4);
+            sb[i] = Us.load(36 + i, ub4[i]);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const half2_t u = U.load(i * 9 + k, us);
-            const half2_t w = U.load(i * 9 + k, ub_off[i]);
-            fre[i][k] = half2_t{u.x, (_Float16)(-u.y)};
-            fim[i][k] = half2_t{u.y, u.x};
-            bre[i][k] = w;
-            bim[i][k] = half2_t{(_Float16)(-w.y), w.x};
+            for (int k = 0; k < 9; ++k) {
+                const half2_t uu = u[9 * i + k], ww = w[i][k];
+                fre[i][k] = half2_t{uu.x, (_Float16)(-uu.y)};
+                fim[i][k] = half2_t{uu.y, uu.x};
+                bre[i][k] = ww;
+                bim[i][k] = half2_t{(_Float16)(-ww.y), ww.x};
+            }
         }
     }
 
     for (int c = c0; c < c1; ++c) {
-        const FieldRef<half2_t, BUF> src(job.src[c]);
+        const ChunkRef<BUF> src(job.src[c]);
         const FieldRef<float, BUF> ssc(job.src[c]);
-        // Load phase: every neighbour record of this column (6 x 12 half2 and
+        // Load phase: every neighbour record of this column (6 x 3 chunks and
         // their scales) and the site's own record are requested before any
         // arithmetic, so the wavefront waits for memory once per column.
         half2_t v[6][12], own[12];
         float vsc[6], so;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                v[2 * i][k] = src.load(k, cf[i]);
-                v[2 * i + 1][k] = src.load(k, cb[i]);
-            }
-            vsc[2 * i] = ssc.load(12, cf[i]);
-            vsc[2 * i + 1] = ssc.load(12, cb[i]);
+            load_elems<0, 12>(src, cf[i], v[2 * i]);
+            load_elems<0, 12>(src, cb[i], v[2 * i + 1]);
+            vsc[2 * i] = ssc.load(12, cf4[i]);
+            vsc[2 * i + 1] = ssc.load(12, cb4[i]);
         }
-#pragma unroll
-        for (int k = 0; k < 12; ++k) own[k] = src.load(k, cs);
-        so = ssc.load(12, cs);
+        load_elems<0, 12>(src, cs, own);
+        so = ssc.load(12, cs4);
         __builtin_amdgcn_sched_barrier(0);
 
         float2 acc[12];
@@ -262,11 +268,11 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
             m = fmaxf(m, fmaxf(fabsf(out[k].x), fabsf(out[k].y)));
         }
         const int e = f16s_exponent(m);
-        const FieldRef<half2_t, BUF> dst(job.dst[c]);
-        const FieldRef<float, BUF> dsc(job.dst[c]);
+        half2_t q[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) dst.store(f16s_encode(out[k].x, out[k].y, e), k, cs);
-        dsc.store(m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f, 12, cs);
+        for (int k = 0; k < 12; ++k) q[k] = f16s_encode(out[k].x, out[k].y, e);
+        store_elems<12>(ChunkRef<BUF>(job.dst[c]), cs, q);
+        FieldRef<float, BUF>(job.dst[c]).store(m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f, 12, cs4);
     }
 }
 
