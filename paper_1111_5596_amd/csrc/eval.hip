@@ -180,6 +180,43 @@ __device__ __forceinline__ cplx_t<R> load_comp(const char* base, int32_t prec, i
     }
 }
 
+// N consecutive components of record rec (from component 0): whole 16-byte
+// chunks when the record starts on a chunk boundary of a chunked field (F32:
+// 2 components per load, F16S: 4), else one component at a time.
+template <typename R, int N>
+__device__ __forceinline__ void load_comps(const char* base, int32_t prec, int32_t nrec, int32_t ncomp, int32_t rec,
+                                           int32_t site, cplx_t<R>* v) {
+    using T2 = cplx_t<R>;
+    const int32_t e0 = rec * ncomp;
+    if constexpr (N % 2 == 0) {
+        if (prec == QDP_F32 && chunked_layout(nrec, ncomp, prec) && e0 % 2 == 0) {
+            const char* p = base + comp_offset(nrec, ncomp, prec, rec, 0, site);
+#pragma unroll
+            for (int q = 0; q < N / 2; ++q) {
+                const float4 w = *reinterpret_cast<const float4*>(p + q * 1024);
+                v[2 * q] = T2{(R)w.x, (R)w.y};
+                v[2 * q + 1] = T2{(R)w.z, (R)w.w};
+            }
+            return;
+        }
+    }
+    if constexpr (N % 4 == 0) {
+        if (prec == QDP_F16S && chunked_layout(nrec, ncomp, prec) && e0 % 4 == 0) {
+            const char* p = base + comp_offset(nrec, ncomp, prec, rec, 0, site);
+            const float sc = *reinterpret_cast<const float*>(base + scale_offset(nrec, ncomp, rec, site));
+#pragma unroll
+            for (int q = 0; q < N / 4; ++q) {
+                const Chunk<half2_t> w = __builtin_bit_cast(Chunk<half2_t>, *reinterpret_cast<const u32x4_t*>(p + q * 1024));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[4 * q + j] = T2{(R)((float)w.v[j].x * sc), (R)((float)w.v[j].y * sc)};
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = load_comp<R>(base, prec, nrec, ncomp, rec, k, site);
+}
+
 template <int T, typename R>
 __device__ __forceinline__ void load_operand(const Operand& op, const Geometry& g, int32_t s,
                                              const int32_t c[4], cplx_t<R>* v) {
@@ -190,8 +227,7 @@ __device__ __forceinline__ void load_operand(const Operand& op, const Geometry& 
         return;
     }
     const int32_t site = op.has_disp ? displaced_site(g, c, op.d) : s;
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = load_comp<R>(op.base, op.prec, op.nrec, op.ncomp, op.rec, k, site);
+    load_comps<R, N>(op.base, op.prec, op.nrec, op.ncomp, op.rec, site, v);
 }
 
 template <typename R>
@@ -203,6 +239,15 @@ __device__ __forceinline__ void store_values(const OutDesc& out, const Geometry&
             *reinterpret_cast<double2*>(out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, k, s)) = w;
         }
     } else if (out.prec == QDP_F32) {
+        if (N % 2 == 0 && chunked_layout(out.nrec, out.ncomp, out.prec)) {
+            // whole 16-byte chunks (the output record starts the site's chunks)
+            char* p = out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, 0, s);
+            for (int q = 0; q < N / 2; ++q)
+                *reinterpret_cast<float4*>(p + q * 1024) =
+                    make_float4((float)v[2 * q].x, out.real_only ? 0.f : (float)v[2 * q].y, (float)v[2 * q + 1].x,
+                                out.real_only ? 0.f : (float)v[2 * q + 1].y);
+            return;
+        }
         for (int k = 0; k < N; ++k) {
             float2 w = make_float2((float)v[k].x, out.real_only ? 0.f : (float)v[k].y);
             *reinterpret_cast<float2*>(out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, k, s)) = w;
@@ -468,9 +513,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs A) {
         const StencilTerm& T = A.t[term];
         T2 v[NV];
         const int32_t vs = T.vec.has_disp ? displaced_site(A.g, c, T.vec.d) : s;
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            v[k] = load_comp<R>(T.vec.base, T.vec.prec, T.vec.nrec, T.vec.ncomp, T.vec.rec, k, vs);
+        load_comps<R, NV>(T.vec.base, T.vec.prec, T.vec.nrec, T.vec.ncomp, T.vec.rec, vs, v);
         T2 w[NV];
         if (T.has_mat) {
             T2 m[9];
