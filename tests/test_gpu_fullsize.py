@@ -97,6 +97,81 @@ def test_16cubed_32_point_source_pion_and_rho(qdp):
             qdp.free(f)
 
 
+def test_16cubed_32_sink_smeared_synthetic_propagator(qdp):
+    """16^3 x 32, links seed 2: the synthetic 12-column propagator (seed 102)
+    sink-smeared with kappa 0.25, N 50 (FP32), pion (n = 15) and rho (n = 1,
+    2, 4) correlators; the oracle smears slices 0 and 19 and contracts them."""
+    dims = (16, 16, 16, 32)
+    V = synth.volume(dims)
+    sd = (16, 16, 16, 1)
+    lat = qdp.lattice(dims)
+    g = qdp.alloc(lat, "GAUGE", "F32")
+    qdp.fill_random_su3(g, 2)
+    cols = [qdp.alloc(lat, "FERMION", "F32") for _ in range(12)]
+    for j, f in enumerate(cols):
+        qdp.fill_gaussian(f, 102, j, (24.0 * V) ** -0.5)
+    try:
+        qdp.smear(g, cols, 0.25, 50, mode=1)
+        C = qdp.contract(cols, cols)
+        for t in (0, 19):
+            U = synth.su3_links(dims, 2, t_range=(t, t + 1))
+            P = synth.gaussian_propagator(dims, 102, t_range=(t, t + 1))
+            Sref = oracle.smear(U, P, sd, 0.25, 50)
+            got = np.stack([qdp.read_timeslices(f, t, t + 1) for f in cols])
+            assert np.linalg.norm(got - Sref) <= 1e-5 * np.linalg.norm(Sref)
+            Cref = oracle.meson(Sref, Sref, sd)[:, 0]
+            c15 = Cref[15].real
+            for n in (15, 1, 2, 4):
+                assert abs(C[n, t] - Cref[n]) <= 1e-5 * c15, (t, n)
+    finally:
+        for f in [g] + cols:
+            qdp.free(f)
+
+
+def test_24cubed_48_chain_f16s_against_fp32_and_oracle(qdp):
+    """24^3 x 48, links seed 3: source smearing of a 12-column point source
+    (N 50), the synthetic propagator (seed 103) sink-smeared (N 50) and all 16
+    bilinears, once with F16S storage and once with FP32 storage.  The oracle
+    checks the smeared source on its slice, the smeared propagator and the
+    correlators on slice 11; F16S and FP32 correlators agree to 2e-3 of
+    C_15 on every slice."""
+    dims = (24, 24, 24, 48)
+    V = synth.volume(dims)
+    sd = (24, 24, 24, 1)
+    t = 11
+    U_src = synth.su3_links(dims, 3, t_range=(0, 1))
+    src_ref = oracle.smear(U_src, synth.point_source(sd, range(12)), sd, 0.25, 50)
+    U = synth.su3_links(dims, 3, t_range=(t, t + 1))
+    snk_ref = oracle.smear(U, synth.gaussian_propagator(dims, 103, t_range=(t, t + 1)), sd, 0.25, 50)
+    C_ref = oracle.meson(snk_ref, snk_ref, sd)[:, 0]
+    lat = qdp.lattice(dims)
+    corr = {}
+    for prec, tol in (("F32", 1e-5), ("F16S", 2e-3)):
+        g = qdp.alloc(lat, "GAUGE", prec)
+        qdp.fill_random_su3(g, 3)
+        src = [qdp.alloc(lat, "FERMION", prec) for _ in range(12)]
+        snk = [qdp.alloc(lat, "FERMION", prec) for _ in range(12)]
+        try:
+            for j, f in enumerate(src):
+                qdp.fill_point(f, 0, j // 3, j % 3)
+            qdp.smear(g, src, 0.25, 50, mode=1)
+            got = np.stack([qdp.read_timeslices(f, 0, 1) for f in src])
+            assert np.linalg.norm(got - src_ref) <= tol * np.linalg.norm(src_ref), prec
+            for j, f in enumerate(snk):
+                qdp.fill_gaussian(f, 103, j, (24.0 * V) ** -0.5)
+            qdp.smear(g, snk, 0.25, 50, mode=1)
+            got = np.stack([qdp.read_timeslices(f, t, t + 1) for f in snk])
+            assert np.linalg.norm(got - snk_ref) <= tol * np.linalg.norm(snk_ref), prec
+            C = qdp.contract(snk, snk)
+            assert np.max(np.abs(C[:, t] - C_ref)) <= tol * C_ref[15].real, prec
+            corr[prec] = C
+        finally:
+            for f in [g] + src + snk:
+                qdp.free(f)
+    c15 = corr["F32"][15].real
+    assert np.max(np.abs(corr["F16S"] - corr["F32"]) / c15[None, :]) <= 2e-3
+
+
 def test_batch_of_64_uneven_lattices(qdp):
     """64 lattices drawn from {8^3x16, 12^3x24, 16^3x32, 24^3x48}, links seed
     4001 + l, 12-column point sources, kappa 0.25, N 30, one persistent launch
