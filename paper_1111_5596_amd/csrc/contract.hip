@@ -297,11 +297,13 @@ __device__ __forceinline__ double2 times_ik(double2 z, int k) {
     }
 }
 
-// X[r][r'] = component (r, a) of column 3 r' + ap at checkerboard site s.
-// Component 3 r + a lies in chunk (3 r + a) / CE at position (3 r + a) % CE;
-// with a known only at run time each component is one element-sized load.
-template <int PREC, bool BUF>
-__device__ __forceinline__ void load_block(const char* const* cols, int a, int ap, int32_t s, double2 X[4][4]) {
+// X[r][r'] = component (r, A) of column 3 r' + AP at checkerboard site s.
+// Component 3 r + A lies in chunk (3 r + A) / CE at position (3 r + A) % CE
+// (CE = components per 16-byte chunk), known at compile time: the chunks a
+// column contributes are loaded whole (the compiler merges repeated loads
+// of one chunk) and the components picked out of them.
+template <int PREC, bool BUF, int A, int AP>
+__device__ __forceinline__ void load_block(const char* const* cols, int32_t s, double2 X[4][4]) {
     using T = typename std::conditional<PREC == QDP_F64, double2,
                                         typename std::conditional<PREC == QDP_F32, float2, half2_t>::type>::type;
     constexpr int CE = 16 / sizeof(T);
@@ -309,16 +311,15 @@ __device__ __forceinline__ void load_block(const char* const* cols, int a, int a
     const int64_t so16 = tile_site_offset(tb, 16, s);
 #pragma unroll
     for (int rp = 0; rp < 4; ++rp) {
-        const char* base = cols[3 * rp + ap];
-        const FieldRef<T, BUF> f(base);
+        const char* base = cols[3 * rp + AP];
+        const ChunkRef<BUF> f(base);
         float scale = 1.f;
         if constexpr (PREC == QDP_F16S) scale = FieldRef<float, BUF>(base).load(12, site_off<float>(s, tb));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int e = 3 * r + a;
-            // FieldRef rows are 64 elements apart; a chunk row is 64 * 16 bytes
-            const int64_t off = so16 + (int64_t)(e % CE) * (int64_t)sizeof(T);
-            const T v = f.load((e / CE) * CE, off);
+            const int e = 3 * r + A;
+            const Chunk<T> c = __builtin_bit_cast(Chunk<T>, f.load(e / CE, so16));
+            const T v = c.v[e % CE];
             if constexpr (PREC == QDP_F16S) {
                 const float2 d = f16s_decode(v, scale);
                 X[r][rp] = make_double2(d.x, d.y);
@@ -392,6 +393,35 @@ __device__ __forceinline__ double2 pair_term(const double2 X[4][4], const double
     return make_double2(f.x + a.x + b.x, f.y + a.y + b.y);
 }
 
+// One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ].
+template <int PREC, bool BUF, int B, int BP>
+__device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, double hp) {
+    constexpr int X0 = B == 0 ? 1 : 0, Y0 = B == 2 ? 1 : 2;
+    constexpr int XP = BP == 0 ? 1 : 0, YP = BP == 2 ? 1 : 2;
+    // (x, b, y) is an even permutation of (0, 1, 2) only for b = 1
+    constexpr double SG = (B == 1 ? 1.0 : -1.0) * (BP == 1 ? 1.0 : -1.0);
+    double2 M[4][4];
+    {
+        double2 D[4][4];
+        load_block<PREC, BUF, B, BP>(A.sd, s, D);
+        // M = Cg5 D G' with G' = -Cg5:
+        // M[r][perm[q]] = -i^(code[r] + code[q]) D[perm[r]][q]
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                M[r][kCg5.perm[q]] = times_ik(D[kCg5.perm[r]][q], kCg5.code[r] + kCg5.code[q] + 2);
+    }
+    double2 X[4][4], Y[4][4];
+    load_block<PREC, BUF, X0, XP>(A.su, s, X);
+    load_block<PREC, BUF, Y0, YP>(A.su, s, Y);
+    const double2 f1 = pair_term(X, Y, M, hp);
+    load_block<PREC, BUF, X0, YP>(A.su, s, X);
+    load_block<PREC, BUF, Y0, XP>(A.su, s, Y);
+    const double2 f2 = pair_term(X, Y, M, hp);
+    return make_double2(SG * (f1.x - f2.x), SG * (f1.y - f2.y));
+}
+
 template <int PREC, bool BUF>
 __global__ __launch_bounds__(256) void nucleon_kernel(BaryonArgs A) {
     const int t = blockIdx.y;
@@ -403,34 +433,24 @@ __global__ __launch_bounds__(256) void nucleon_kernel(BaryonArgs A) {
     for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
+        // the nine colour steps run one after another (a runtime loop, so the
+        // compiler keeps one step's blocks live at a time)
 #pragma unroll 1
         for (int bb = 0; bb < 9; ++bb) {
-            const int b = bb / 3, bp = bb % 3;
-            const int x = b == 0 ? 1 : 0, y = b == 2 ? 1 : 2;
-            const int xp = bp == 0 ? 1 : 0, yp = bp == 2 ? 1 : 2;
-            // (x, b, y) is an even permutation of (0, 1, 2) only for b = 1
-            const double sg = (b == 1 ? 1.0 : -1.0) * (bp == 1 ? 1.0 : -1.0);
-            double2 M[4][4];
-            {
-                double2 D[4][4];
-                load_block<PREC, BUF>(A.sd, b, bp, s, D);
-                // M = Cg5 D G' with G' = -Cg5:
-                // M[r][perm[q]] = -i^(code[r] + code[q]) D[perm[r]][q]
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        M[r][kCg5.perm[q]] = times_ik(D[kCg5.perm[r]][q], kCg5.code[r] + kCg5.code[q] + 2);
+            double2 d;
+            switch (__builtin_amdgcn_readfirstlane(bb)) {
+                case 0: d = colour_step<PREC, BUF, 0, 0>(A, s, hp); break;
+                case 1: d = colour_step<PREC, BUF, 0, 1>(A, s, hp); break;
+                case 2: d = colour_step<PREC, BUF, 0, 2>(A, s, hp); break;
+                case 3: d = colour_step<PREC, BUF, 1, 0>(A, s, hp); break;
+                case 4: d = colour_step<PREC, BUF, 1, 1>(A, s, hp); break;
+                case 5: d = colour_step<PREC, BUF, 1, 2>(A, s, hp); break;
+                case 6: d = colour_step<PREC, BUF, 2, 0>(A, s, hp); break;
+                case 7: d = colour_step<PREC, BUF, 2, 1>(A, s, hp); break;
+                default: d = colour_step<PREC, BUF, 2, 2>(A, s, hp); break;
             }
-            double2 X[4][4], Y[4][4];
-            load_block<PREC, BUF>(A.su, x, xp, s, X);
-            load_block<PREC, BUF>(A.su, y, yp, s, Y);
-            const double2 f1 = pair_term(X, Y, M, hp);
-            load_block<PREC, BUF>(A.su, x, yp, s, X);
-            load_block<PREC, BUF>(A.su, y, xp, s, Y);
-            const double2 f2 = pair_term(X, Y, M, hp);
-            acc.x += sg * (f1.x - f2.x);
-            acc.y += sg * (f1.y - f2.y);
+            acc.x += d.x;
+            acc.y += d.y;
         }
     }
     __shared__ double red[4][2];
