@@ -56,6 +56,8 @@ def _load():
     lib.or_meson_mom.restype = ctypes.c_int32
     lib.or_nucleon.argtypes = [_i32p, _dp, _dp, ctypes.c_int32, _dp]
     lib.or_nucleon.restype = ctypes.c_int32
+    lib.or_delta.argtypes = [_i32p, _dp, ctypes.c_int32, _dp]
+    lib.or_delta.restype = ctypes.c_int32
     lib.or_timeslice_sum.argtypes = [_i32p, ctypes.c_int32, _dp, _dp]
     lib.or_timeslice_sum.restype = None
     lib.or_norm2.argtypes = [ctypes.c_int64, _dp]
@@ -182,6 +184,22 @@ def nucleon(Su, Sd, dims, parity=1) -> np.ndarray:
                             int(parity), _dptr(out.view(np.float64)))
     if rc != 0:
         raise MemoryError("oracle nucleon: allocation failed")
+    return out
+
+
+def delta(S, dims, parity=1) -> np.ndarray:
+    """Delta++ two-point function C(t), shape (Lt,) complex128, summed over
+    the spatial mu and projected with (1 + parity gamma_4)/2; S has shape
+    (12, V, 4, 3) (the u propagator)."""
+    a = _c128(S)
+    V = volume(dims)
+    assert a.shape == (12, V, 4, 3) and parity in (1, -1)
+    out = np.zeros(int(dims[3]), dtype=np.complex128)
+    d = _dims(dims)
+    rc = _load().or_delta(d.ctypes.data_as(_i32p), _dptr(a.view(np.float64)), int(parity),
+                          _dptr(out.view(np.float64)))
+    if rc != 0:
+        raise MemoryError("oracle delta: allocation failed")
     return out
 
 

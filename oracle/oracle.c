@@ -457,6 +457,106 @@ int32_t or_nucleon(const int32_t d[4], const double* Su, const double* Sd, int32
 }
 
 /* ------------------------------------------------------------------------ */
+/* Delta++ two-point function (three identical quarks, u u u).               */
+/*                                                                           */
+/*   chi^mu_g(x)     = eps_{abc} (C gamma_mu)_{rs} u^a_r u^b_s u^c_g          */
+/*   chibar^mu_g'(0) = eps_{a'b'c'} ubar^{c'}_g' ubar^{b'}_s' G'_{s'r'} ubar^{a'}_r' */
+/* with G' = gamma_4 (C gamma_mu)^dagger gamma_4^T (the Dirac adjoint) and   */
+/* C = gamma_2 gamma_4.  With q1 = (a r), q2 = (b s), q3 = (c g) at the sink */
+/* and q1' = (a' r'), q2' = (b' s'), q3' = (c' g') at the source, Wick's     */
+/* theorem gives <q1 q2 q3 qbar3' qbar2' qbar1'> = det_{ij} S(q_i, q_j'), the */
+/* identity pairing counted +.  The result, projected with                   */
+/* P = (1 + parity gamma_4)/2 and summed over the spatial mu = 1, 2, 3, is   */
+/*   C(t) = sum_{x: x_3 = t} sum_mu sum_{g g'} P_{g'g} <chi^mu_g chibar^mu_g'>. */
+/* Written with dense 4x4 matrices and plain loops.  out is [Lt][re, im].     */
+/* ------------------------------------------------------------------------ */
+
+int32_t or_delta(const int32_t d[4], const double* S, int32_t parity, double* out) {
+    const int64_t V = volume(d);
+    const int32_t Lt = d[3];
+    const int64_t Vs = V / Lt;
+    static const int perms[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+    static const double psign[6] = {1, 1, 1, -1, -1, -1};
+    cplx g[5][4][4], Cm[4][4], G[3][4][4], Gp[3][4][4], P[4][4], T[4][4];
+    gamma_n(1, g[1]);
+    gamma_n(2, g[2]);
+    gamma_n(4, g[3]);
+    gamma_n(8, g[4]);
+    mat4_mul(g[2], g[4], Cm);
+    for (int mu = 0; mu < 3; ++mu) {
+        mat4_mul(Cm, g[mu + 1], G[mu]);
+        /* G' = gamma_4 G^dagger gamma_4^T */
+        cplx Gd[4][4], g4t[4][4];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                Gd[i][j] = c_conj(G[mu][j][i]);
+                g4t[i][j] = g[4][j][i];
+            }
+        mat4_mul(g[4], Gd, T);
+        mat4_mul(T, g4t, Gp[mu]);
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            P[i][j] = c_scale(0.5 * parity, g[4][i][j]);
+            if (i == j) P[i][j].re += 0.5;
+        }
+    cplx* site_val = (cplx*)malloc(sizeof(cplx) * (size_t)V);
+    if (!site_val) return -1;
+
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < V; ++s) {
+        cplx total = c_make(0.0, 0.0);
+        for (int mu = 0; mu < 3; ++mu)
+            for (int i = 0; i < 6; ++i)
+                for (int j = 0; j < 6; ++j) {
+                    const int a = perms[i][0], b = perms[i][1], c = perms[i][2];
+                    const int ap = perms[j][0], bp = perms[j][1], cp = perms[j][2];
+                    const double sg = psign[i] * psign[j];
+                    for (int r = 0; r < 4; ++r)
+                        for (int sp = 0; sp < 4; ++sp) {
+                            const cplx gs = G[mu][r][sp];
+                            if (gs.re == 0.0 && gs.im == 0.0) continue;
+                            for (int spp = 0; spp < 4; ++spp)
+                                for (int rp = 0; rp < 4; ++rp) {
+                                    const cplx gps = Gp[mu][spp][rp];
+                                    if (gps.re == 0.0 && gps.im == 0.0) continue;
+                                    for (int gm = 0; gm < 4; ++gm)
+                                        for (int gmp = 0; gmp < 4; ++gmp) {
+                                            const cplx pp = P[gmp][gm];
+                                            if (pp.re == 0.0 && pp.im == 0.0) continue;
+                                            /* rows: sink quarks (a r), (b sp), (c gm);
+                                               columns: source quarks (a' rp), (b' spp), (c' gmp) */
+                                            const int row[3] = {3 * r + a, 3 * sp + b, 3 * gm + c};
+                                            const int col[3] = {3 * rp + ap, 3 * spp + bp, 3 * gmp + cp};
+                                            cplx m[3][3];
+                                            for (int x = 0; x < 3; ++x)
+                                                for (int y = 0; y < 3; ++y) m[x][y] = prop_elem(S, V, s, row[x], col[y]);
+                                            const cplx det = c_add(
+                                                c_add(c_mul(m[0][0], c_add(c_mul(m[1][1], m[2][2]),
+                                                                          c_scale(-1.0, c_mul(m[1][2], m[2][1])))),
+                                                      c_scale(-1.0, c_mul(m[0][1], c_add(c_mul(m[1][0], m[2][2]),
+                                                                                         c_scale(-1.0, c_mul(m[1][2], m[2][0])))))),
+                                                c_mul(m[0][2], c_add(c_mul(m[1][0], m[2][1]),
+                                                                     c_scale(-1.0, c_mul(m[1][1], m[2][0])))));
+                                            const cplx coef = c_mul(c_mul(gs, gps), pp);
+                                            total = c_add(total, c_scale(sg, c_mul(coef, det)));
+                                        }
+                                }
+                        }
+                }
+        site_val[s] = total;
+    }
+    for (int32_t t = 0; t < Lt; ++t) {
+        cplx acc = c_make(0.0, 0.0);
+        for (int64_t k = 0; k < Vs; ++k) acc = c_add(acc, site_val[t * Vs + k]);
+        out[2 * t] = acc.re;
+        out[2 * t + 1] = acc.im;
+    }
+    free(site_val);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sums (global and time-slice), FP64, sequential over lexicographic sites.  */
 /* ------------------------------------------------------------------------ */
 

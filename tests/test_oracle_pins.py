@@ -566,6 +566,91 @@ def test_nucleon_gauge_invariance_and_parity_sum():
     assert np.abs(Ct - Ctg).max() > 1e-3 * np.abs(Ct).max()
 
 
+def _delta_gammas(parity):
+    g1, g2, g3, g4 = _DR
+    C = g2 @ g4
+    G = [C @ g for g in (g1, g2, g3)]
+    Gp = [g4 @ x.conj().T @ g4.T for x in G]
+    P = 0.5 * (np.eye(4) + parity * g4)
+    return G, Gp, P
+
+
+def _delta_by_wick(S, dims, parity):
+    """Delta++ correlator as the six Wick terms of <q1 q2 q3 qbar3' qbar2' qbar1'>
+    written out one by one (einsum over every index), summed over mu = 1..3."""
+    G, Gp, P = _delta_gammas(parity)
+    eps = _levi_civita()
+    V = synth.volume(dims)
+    U = np.transpose(S.reshape(4, 3, V, 4, 3), (2, 3, 4, 0, 1))  # U[x, r, a, R, A]
+    # sink quarks (a r), (b s), (c g); source quarks (A R), (B S), (C G)
+    terms = [("xraRA,xsbSB,xgcGC", 1), ("xraSB,xsbRA,xgcGC", -1), ("xraGC,xsbSB,xgcRA", -1),
+             ("xraRA,xsbGC,xgcSB", -1), ("xraSB,xsbGC,xgcRA", 1), ("xraGC,xsbRA,xgcSB", 1)]
+    site = np.zeros(V, dtype=np.complex128)
+    for mu in range(3):
+        for t, sg in terms:
+            site += sg * np.einsum("abc,rs,ABC,SR,Gg," + t + "->x", eps, G[mu], eps, Gp[mu], P, U, U, U,
+                                   optimize=True)
+    return site.reshape(dims[3], -1).sum(axis=1)
+
+
+@pytest.mark.parametrize("parity", [1, -1])
+def test_delta_matches_wick_terms(parity):
+    dims = (2, 2, 2, 3)
+    S = synth.gaussian_propagator(dims, 183)
+    got = oracle.delta(S, dims, parity)
+    ref = _delta_by_wick(S, dims, parity)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_delta_free_point_source_closed_form():
+    """Unit links, 12-column point source: S = phi(x) 1_12.  The colour sums
+    give 6 for every Wick term, and the spin sums reduce each term to a trace:
+    C(t0) = 6 sum_x phi^3 sum_mu [Tr(G G') Tr P + Tr(G G'^T) Tr P + Tr(G G' P^T)
+    + Tr(G P G') + Tr(G P G'^T) + Tr(G G'^T P^T)], with sum_x phi^3 from the
+    Brillouin-zone double convolution."""
+    dims = (4, 6, 2, 4)
+    N = 4
+    S = oracle.smear(unit_links(dims), synth.point_source(dims, range(12)), dims, 0.25, N)
+    L = dims[:3]
+    Q = np.meshgrid(*[2 * np.pi * np.arange(l) / l for l in L], indexing="ij")
+    lam = (1 + 0.5 * (np.cos(Q[0]) + np.cos(Q[1]) + np.cos(Q[2]))) ** N
+    Vs = L[0] * L[1] * L[2]
+    flat = lam.reshape(-1)
+    idx = np.indices(L).reshape(3, -1)
+    cube = 0.0
+    for i in range(Vs):
+        k = (idx[:, i:i + 1] + idx) % np.array(L)[:, None]
+        cube += flat[i] * np.sum(flat * lam[k[0], k[1], k[2]])
+    cube /= Vs ** 2
+    for parity in (1, -1):
+        G, Gp, P = _delta_gammas(parity)
+        K = 0
+        for g, gp in zip(G, Gp):
+            K += (np.trace(g @ gp) * np.trace(P) + np.trace(g @ gp.T) * np.trace(P) + np.trace(g @ gp @ P.T)
+                  + np.trace(g @ P @ gp) + np.trace(g @ P @ gp.T) + np.trace(g @ gp.T @ P.T))
+        assert abs(K) > 1.0  # the pin is not trivially zero
+        C = oracle.delta(S, dims, parity)
+        assert abs(C[0] - 6 * K * cube) <= 1e-12 * abs(6 * K * cube)
+        assert np.count_nonzero(C[1:]) == 0
+
+
+def test_delta_gauge_invariance():
+    dims = (4, 2, 2, 3)
+    S = synth.gaussian_propagator(dims, 193)
+    g = synth.gauge_transform(dims, 9193)
+    C = oracle.delta(S, dims, 1)
+    Cg = oracle.delta(gauge_rotate_fermions(g, S), dims, 1)
+    assert np.abs(C - Cg).max() <= 1e-13 * np.abs(C).max()
+
+    # a U(3) rotation exp(i theta(t)) g(x) at the sink multiplies C(t) by the
+    # determinant exp(3 i theta(t)): exactly one epsilon tensor at the sink
+    theta = np.array([0.3, -1.1, 2.0])
+    Vs = 16
+    ph = np.repeat(np.exp(1j * theta), Vs)[:, None, None] * g
+    Cu = oracle.delta(gauge_rotate_fermions(ph, S), dims, 1)
+    assert np.abs(Cu - np.exp(3j * theta) * C).max() <= 1e-13 * np.abs(C).max()
+
+
 def test_config1_pion_is_column_norm_per_slice():
     """The one-column pion correlator C(t) = sum_x |psi(x, t)|^2 is the n = 15
     term restricted to column 0 (the other columns zero)."""
