@@ -180,15 +180,17 @@ def run_batch64(q, torch):
 def run_hadron_extras(q, torch, lat, V):
     """Wall time of the other hadron contractions on the same 48^3x96 F16S
     propagator (12 Gaussian columns): zero-momentum mesons, mesons at the
-    four momenta (0,0,0), (1,0,0), (0,1,0), (0,0,1) in one launch, and the
-    proton two-point function.  Each call synchronises; the median of 3."""
+    four momenta (0,0,0), (1,0,0), (0,1,0), (0,0,1) in one launch, the proton
+    and the Delta++ two-point functions.  Each call synchronises; the median
+    of 3."""
     cols = [q.alloc(lat, "FERMION", "F16S") for _ in range(12)]
     for j, f in enumerate(cols):
         q.fill_gaussian(f, 105, j, (24.0 * V) ** -0.5)
     moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
     calls = {"meson_p0_ms": lambda: q.contract(cols, cols),
              "meson_4mom_ms": lambda: q.contract_mom(cols, cols, moms),
-             "nucleon_ms": lambda: q.nucleon(cols, cols)}
+             "nucleon_ms": lambda: q.nucleon(cols, cols),
+             "delta_pp_ms": lambda: q.delta(cols)}
     out = {}
     for name, fn in calls.items():
         fn()

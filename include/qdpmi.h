@@ -335,19 +335,23 @@ qdp_status qdp_hadron_contract_mom(qdp_ctx* ctx, const qdp_field* S1, const qdp_
 /* section 5)                                                              */
 /* ---------------------------------------------------------------------- */
 
-enum qdp_baryon_kind { QDP_BARYON_PROTON = 0 };
+enum qdp_baryon_kind { QDP_BARYON_PROTON = 0, QDP_BARYON_DELTA_PP = 1 };
 
-/* Proton two-point function with parity projection,
+/* Baryon two-point functions with parity projection,
  *   C(t) = sum_{x: x_3 = t} sum_{g g'} P_{g'g} < chi_g(x) chibar_g'(0) >,
- *   chi = eps_abc (u_a^T C g5 d_b) u_c,  chibar = chi^dagger gamma_4,
  *   P = (1 + parity gamma_4) / 2,  C = gamma_2 gamma_4 (DeGrand-Rossi),
- * evaluated by Wick's theorem with Su = <u ubar> and Sd = <d dbar> (12
- * FERMION columns each, same layout as qdp_hadron_contract; Sd may equal
- * Su): a direct and an exchange term, no overall fermion sign.  Values are
- * decoded to FP64; products and sums are FP64.  out: Lt * 2 doubles,
- * out[t' * 2 + k] with t' = (t - t0) mod Lt.  Synchronises.  Errors:
- * QDP_ERR_ARG (parity not +-1), QDP_ERR_UNSUPPORTED (kind, j_decay != 3,
- * mixed precisions), QDP_ERR_TYPE, QDP_ERR_LATTICE. */
+ *   chibar = chi^dagger gamma_4, evaluated by Wick's theorem with no
+ *   overall fermion sign:
+ * - QDP_BARYON_PROTON: chi = eps_abc (u_a^T C g5 d_b) u_c with Su = <u ubar>
+ *   and Sd = <d dbar> (Sd may equal Su): a direct and an exchange term;
+ * - QDP_BARYON_DELTA_PP: chi^mu = eps_abc (u_a^T C gamma_mu u_b) u_c, summed
+ *   over mu = 1, 2, 3 (no spin-3/2 projection), three u quarks: the
+ *   determinant of the six pairings; Sd is not read (may be NULL).
+ * Su, Sd: 12 FERMION columns each, the layout of qdp_hadron_contract.
+ * Values are decoded to FP64; products and sums are FP64.  out: Lt * 2
+ * doubles, out[t' * 2 + k] with t' = (t - t0) mod Lt.  Synchronises.
+ * Errors: QDP_ERR_ARG (parity not +-1), QDP_ERR_UNSUPPORTED (kind,
+ * j_decay != 3, mixed precisions), QDP_ERR_TYPE, QDP_ERR_LATTICE. */
 qdp_status qdp_baryon_contract(qdp_ctx* ctx, const qdp_field* Su, const qdp_field* Sd, int32_t kind,
                                int32_t parity, int32_t t0, int32_t j_decay, double* out);
 

@@ -53,6 +53,36 @@ constexpr SignedPerm kGamma5 =
     sp_mul(sp_mul(sp_mul(kGammaBasis[0], kGammaBasis[1]), kGammaBasis[2]), kGammaBasis[3]);
 // charge conjugation C = gamma_2 gamma_4 times gamma_5
 constexpr SignedPerm kCg5 = sp_mul(sp_mul(kGammaBasis[1], kGammaBasis[3]), kGamma5);
+// Hermitian conjugate and transpose of a signed permutation
+constexpr SignedPerm sp_adj(const SignedPerm& A) {
+    SignedPerm C{};
+    for (int r = 0; r < 4; ++r) {
+        C.perm[A.perm[r]] = r;
+        C.code[A.perm[r]] = (4 - A.code[r]) & 3;
+    }
+    return C;
+}
+constexpr SignedPerm sp_trans(const SignedPerm& A) {
+    SignedPerm C{};
+    for (int r = 0; r < 4; ++r) {
+        C.perm[A.perm[r]] = r;
+        C.code[A.perm[r]] = A.code[r];
+    }
+    return C;
+}
+constexpr SignedPerm sp_neg(const SignedPerm& A) {
+    SignedPerm C = A;
+    for (int r = 0; r < 4; ++r) C.code[r] = (A.code[r] + 2) & 3;
+    return C;
+}
+// diquark matrices at the sink (G) and the source (G' = gamma_4 G^dagger gamma_4^T):
+// proton C gamma_5 (G' = -C gamma_5), Delta++ C gamma_mu for mu = 1, 2, 3
+constexpr SignedPerm kCgamma[3] = {sp_mul(sp_mul(kGammaBasis[1], kGammaBasis[3]), kGammaBasis[0]),
+                                   sp_mul(sp_mul(kGammaBasis[1], kGammaBasis[3]), kGammaBasis[1]),
+                                   sp_mul(sp_mul(kGammaBasis[1], kGammaBasis[3]), kGammaBasis[2])};
+constexpr SignedPerm source_diquark(const SignedPerm& G) {
+    return sp_mul(sp_mul(kGammaBasis[3], sp_adj(G)), sp_trans(kGammaBasis[3]));
+}
 constexpr SignedPerm kGamma4 = kGammaBasis[3];
 
 struct GammaDev {
@@ -384,18 +414,36 @@ __device__ __forceinline__ double2 xpy_m(const double2 X[4][4], const double2 Y[
     return z;
 }
 
+// WD (Tr[P Y] <X, M> + Tr[P X] <Y, M>) + WE (<X P Y, M> + <Y P X, M>): the
+// direct and the exchange terms with their weights (1, 1 for the proton).
+template <int WD, int WE>
 __device__ __forceinline__ double2 pair_term(const double2 X[4][4], const double2 Y[4][4], const double2 M[4][4],
                                             double hp) {
     double2 f = cmul(trace_p(Y, hp), inner_plain(X, M));
     cmac(f, trace_p(X, hp), inner_plain(Y, M));
     const double2 a = xpy_m(X, Y, M, hp);
     const double2 b = xpy_m(Y, X, M, hp);
-    return make_double2(f.x + a.x + b.x, f.y + a.y + b.y);
+    return make_double2(WD * f.x + WE * (a.x + b.x), WD * f.y + WE * (a.y + b.y));
 }
 
+// Kinds of baryon: the sink diquark matrix G (the source one follows), the
+// weights of the direct and exchange terms and the number of G summed.
+// Delta++: with three identical quarks the six Wick terms pair up (the
+// diquark tensors are antisymmetric under exchange of the two quarks they
+// hold) into twice the direct and four times the exchange term of the
+// proton form, with D = U.
+template <int KIND, int MU>
+struct BaryonKind {
+    static constexpr SignedPerm G = KIND == QDP_BARYON_PROTON ? kCg5 : kCgamma[MU];
+    static constexpr SignedPerm Gp = KIND == QDP_BARYON_PROTON ? sp_neg(kCg5) : source_diquark(kCgamma[MU]);
+    static constexpr int WD = KIND == QDP_BARYON_PROTON ? 1 : 2;
+    static constexpr int WE = KIND == QDP_BARYON_PROTON ? 1 : 4;
+};
+
 // One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ].
-template <int PREC, bool BUF, int B, int BP>
+template <int PREC, bool BUF, int B, int BP, int KIND, int MU>
 __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, double hp) {
+    using K = BaryonKind<KIND, MU>;
     constexpr int X0 = B == 0 ? 1 : 0, Y0 = B == 2 ? 1 : 2;
     constexpr int XP = BP == 0 ? 1 : 0, YP = BP == 2 ? 1 : 2;
     // (x, b, y) is an even permutation of (0, 1, 2) only for b = 1
@@ -404,26 +452,51 @@ __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, d
     {
         double2 D[4][4];
         load_block<PREC, BUF, B, BP>(A.sd, s, D);
-        // M = Cg5 D G' with G' = -Cg5:
-        // M[r][perm[q]] = -i^(code[r] + code[q]) D[perm[r]][q]
+        // M = G D G' with signed permutations:
+        // M[r][G'.perm[q]] = i^(G.code[r] + G'.code[q]) D[G.perm[r]][q]
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                M[r][kCg5.perm[q]] = times_ik(D[kCg5.perm[r]][q], kCg5.code[r] + kCg5.code[q] + 2);
+                M[r][K::Gp.perm[q]] = times_ik(D[K::G.perm[r]][q], K::G.code[r] + K::Gp.code[q]);
     }
     double2 X[4][4], Y[4][4];
     load_block<PREC, BUF, X0, XP>(A.su, s, X);
     load_block<PREC, BUF, Y0, YP>(A.su, s, Y);
-    const double2 f1 = pair_term(X, Y, M, hp);
+    const double2 f1 = pair_term<K::WD, K::WE>(X, Y, M, hp);
     load_block<PREC, BUF, X0, YP>(A.su, s, X);
     load_block<PREC, BUF, Y0, XP>(A.su, s, Y);
-    const double2 f2 = pair_term(X, Y, M, hp);
+    const double2 f2 = pair_term<K::WD, K::WE>(X, Y, M, hp);
     return make_double2(SG * (f1.x - f2.x), SG * (f1.y - f2.y));
 }
 
-template <int PREC, bool BUF>
-__global__ __launch_bounds__(256) void nucleon_kernel(BaryonArgs A) {
+template <int PREC, bool BUF, int KIND, int MU>
+__device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, double hp) {
+    double2 acc = make_double2(0.0, 0.0);
+    // the nine colour steps run one after another (a runtime loop, so the
+    // compiler keeps one step's blocks live at a time)
+#pragma unroll 1
+    for (int bb = 0; bb < 9; ++bb) {
+        double2 d;
+        switch (__builtin_amdgcn_readfirstlane(bb)) {
+            case 0: d = colour_step<PREC, BUF, 0, 0, KIND, MU>(A, s, hp); break;
+            case 1: d = colour_step<PREC, BUF, 0, 1, KIND, MU>(A, s, hp); break;
+            case 2: d = colour_step<PREC, BUF, 0, 2, KIND, MU>(A, s, hp); break;
+            case 3: d = colour_step<PREC, BUF, 1, 0, KIND, MU>(A, s, hp); break;
+            case 4: d = colour_step<PREC, BUF, 1, 1, KIND, MU>(A, s, hp); break;
+            case 5: d = colour_step<PREC, BUF, 1, 2, KIND, MU>(A, s, hp); break;
+            case 6: d = colour_step<PREC, BUF, 2, 0, KIND, MU>(A, s, hp); break;
+            case 7: d = colour_step<PREC, BUF, 2, 1, KIND, MU>(A, s, hp); break;
+            default: d = colour_step<PREC, BUF, 2, 2, KIND, MU>(A, s, hp); break;
+        }
+        acc.x += d.x;
+        acc.y += d.y;
+    }
+    return acc;
+}
+
+template <int PREC, bool BUF, int KIND>
+__global__ __launch_bounds__(256) void baryon_kernel(BaryonArgs A) {
     const int t = blockIdx.y;
     const int chunk = blockIdx.x;
     const int64_t Vsh = A.g.Vsh;
@@ -433,24 +506,17 @@ __global__ __launch_bounds__(256) void nucleon_kernel(BaryonArgs A) {
     for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
-        // the nine colour steps run one after another (a runtime loop, so the
-        // compiler keeps one step's blocks live at a time)
-#pragma unroll 1
-        for (int bb = 0; bb < 9; ++bb) {
-            double2 d;
-            switch (__builtin_amdgcn_readfirstlane(bb)) {
-                case 0: d = colour_step<PREC, BUF, 0, 0>(A, s, hp); break;
-                case 1: d = colour_step<PREC, BUF, 0, 1>(A, s, hp); break;
-                case 2: d = colour_step<PREC, BUF, 0, 2>(A, s, hp); break;
-                case 3: d = colour_step<PREC, BUF, 1, 0>(A, s, hp); break;
-                case 4: d = colour_step<PREC, BUF, 1, 1>(A, s, hp); break;
-                case 5: d = colour_step<PREC, BUF, 1, 2>(A, s, hp); break;
-                case 6: d = colour_step<PREC, BUF, 2, 0>(A, s, hp); break;
-                case 7: d = colour_step<PREC, BUF, 2, 1>(A, s, hp); break;
-                default: d = colour_step<PREC, BUF, 2, 2>(A, s, hp); break;
-            }
+        if constexpr (KIND == QDP_BARYON_PROTON) {
+            const double2 d = colour_sum<PREC, BUF, KIND, 0>(A, s, hp);
             acc.x += d.x;
             acc.y += d.y;
+        } else {
+            // sum over the spatial mu = 1, 2, 3
+            const double2 d1 = colour_sum<PREC, BUF, KIND, 0>(A, s, hp);
+            const double2 d2 = colour_sum<PREC, BUF, KIND, 1>(A, s, hp);
+            const double2 d3 = colour_sum<PREC, BUF, KIND, 2>(A, s, hp);
+            acc.x += (d1.x + d2.x) + d3.x;
+            acc.y += (d1.y + d2.y) + d3.y;
         }
     }
     __shared__ double red[4][2];
@@ -469,7 +535,7 @@ __global__ __launch_bounds__(256) void nucleon_kernel(BaryonArgs A) {
 }
 
 // out[(t - t0 mod Lt) * 2 + k] = sum over chunks, fixed order.
-__global__ void nucleon_finish(const double* __restrict__ partial, int32_t Lt, int32_t nchunks, int32_t t0,
+__global__ void baryon_finish(const double* __restrict__ partial, int32_t Lt, int32_t nchunks, int32_t t0,
                                double* __restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= Lt) return;
@@ -622,20 +688,27 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
 }
 
 namespace {
-template <bool BUF>
-void* nucleon_func_buf(int prec) {
+template <bool BUF, int KIND>
+void* baryon_func_kind(int prec) {
     switch (prec) {
-        case QDP_F64: return reinterpret_cast<void*>(&nucleon_kernel<QDP_F64, BUF>);
-        case QDP_F32: return reinterpret_cast<void*>(&nucleon_kernel<QDP_F32, BUF>);
-        default: return reinterpret_cast<void*>(&nucleon_kernel<QDP_F16S, BUF>);
+        case QDP_F64: return reinterpret_cast<void*>(&baryon_kernel<QDP_F64, BUF, KIND>);
+        case QDP_F32: return reinterpret_cast<void*>(&baryon_kernel<QDP_F32, BUF, KIND>);
+        default: return reinterpret_cast<void*>(&baryon_kernel<QDP_F16S, BUF, KIND>);
     }
+}
+void* baryon_func(int prec, bool buf, int kind) {
+    if (kind == QDP_BARYON_PROTON) return buf ? baryon_func_kind<true, QDP_BARYON_PROTON>(prec)
+                                              : baryon_func_kind<false, QDP_BARYON_PROTON>(prec);
+    return buf ? baryon_func_kind<true, QDP_BARYON_DELTA_PP>(prec) : baryon_func_kind<false, QDP_BARYON_DELTA_PP>(prec);
 }
 }  // namespace
 
 qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd, int32_t kind, int32_t parity,
                                 int32_t t0, int32_t j_decay, double* out) {
     if (j_decay != 3) return set_error(ctx, QDP_ERR_UNSUPPORTED, "baryon: only j_decay = 3 (time)");
-    if (kind != QDP_BARYON_PROTON) return set_error(ctx, QDP_ERR_UNSUPPORTED, "baryon: unknown kind %d", kind);
+    if (kind != QDP_BARYON_PROTON && kind != QDP_BARYON_DELTA_PP)
+        return set_error(ctx, QDP_ERR_UNSUPPORTED, "baryon: unknown kind %d", kind);
+    if (kind == QDP_BARYON_DELTA_PP) Sd = Su;  // three u quarks: one propagator
     if (parity != 1 && parity != -1) return set_error(ctx, QDP_ERR_ARG, "baryon: parity must be +1 or -1");
     uint64_t lat = 0;
     int32_t prec = -1;
@@ -677,12 +750,12 @@ qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd
     double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
     void* args[] = {&a};
     const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
-    QDP_HIP(ctx, hipLaunchKernel(buf ? nucleon_func_buf<true>(prec) : nucleon_func_buf<false>(prec),
-                                 dim3((unsigned)nchunks, (unsigned)Lt), dim3(256), args, 0, ctx->stream));
-    QDP_CHECK(check_launch(ctx, "nucleon kernel"));
-    hipLaunchKernelGGL(nucleon_finish, dim3((Lt + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
+    QDP_HIP(ctx, hipLaunchKernel(baryon_func(prec, buf, kind), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256),
+                                 args, 0, ctx->stream));
+    QDP_CHECK(check_launch(ctx, "baryon kernel"));
+    hipLaunchKernelGGL(baryon_finish, dim3((Lt + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
                        (int32_t)nchunks, t0, d_out);
-    QDP_CHECK(check_launch(ctx, "nucleon finish kernel"));
+    QDP_CHECK(check_launch(ctx, "baryon finish kernel"));
     double* host;
     QDP_CHECK(host_result_buffer(ctx, out_bytes, &host));
     QDP_HIP(ctx, hipMemcpyAsync(host, d_out, out_bytes, hipMemcpyDeviceToHost, ctx->stream));

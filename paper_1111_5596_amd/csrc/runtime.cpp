@@ -685,7 +685,7 @@ qdp_status qdp_hadron_contract_mom(qdp_ctx* ctx, const qdp_field* S1, const qdp_
 qdp_status qdp_baryon_contract(qdp_ctx* ctx, const qdp_field* Su, const qdp_field* Sd, int32_t kind,
                                int32_t parity, int32_t t0, int32_t j_decay, double* out) {
     if (!ctx) return QDP_ERR_ARG;
-    if (!Su || !Sd || !out) return set_error(ctx, QDP_ERR_ARG, "null argument");
+    if (!Su || (!Sd && kind != QDP_BARYON_DELTA_PP) || !out) return set_error(ctx, QDP_ERR_ARG, "null argument");
     QDP_API_BEGIN
     return baryon_contract_impl(ctx, Su, Sd, kind, parity, t0, j_decay, out);
     QDP_API_END(ctx)

@@ -31,7 +31,7 @@ ASSIGN = {"=": 0, "+=": 1, "-=": 2, "*=": 3}
 SMEAR_FULL, SMEAR_EVEN_ODD = 0, 1
 INIT_NO_AUTOTUNE, INIT_NO_GRAPH = 1, 2
 RANDOM_SU3, RANDOM_GAUSSIAN = 0, 1
-BARYON_PROTON = 0
+BARYON_PROTON, BARYON_DELTA_PP = 0, 1
 OPS = {"field": 0, "gauge": 1, "real_const": 2, "complex_const": 3, "shift": 4, "neg": 5,
        "conj": 6, "adj": 7, "add": 8, "sub": 9, "mul": 10, "gamma_left": 11, "gamma_right": 12,
        "trace": 13, "trace_color": 14, "trace_spin": 15, "real": 16, "imag": 17,
@@ -358,6 +358,15 @@ class Context:
         out = np.zeros(Lt * 2, dtype=np.float64)
         self.check(lib.qdp_baryon_contract(self.h, _u64_array(Su), _u64_array(Sd), BARYON_PROTON, parity, t0,
                                            j_decay, out.ctypes.data_as(_dp)))
+        return out.view(np.complex128)
+
+    def delta(self, S, parity=1, t0=0, j_decay=3):
+        """Delta++ two-point function C(t) (summed over mu = 1, 2, 3), shape (Lt,) complex."""
+        lat = self.field_meta[S[0]][0]
+        Lt = self.lattice_dims[lat][3]
+        out = np.zeros(Lt * 2, dtype=np.float64)
+        self.check(lib.qdp_baryon_contract(self.h, _u64_array(S), None, BARYON_DELTA_PP, parity, t0, j_decay,
+                                           out.ctypes.data_as(_dp)))
         return out.view(np.complex128)
 
     def fill_random_su3(self, gauge, seed):

@@ -212,3 +212,22 @@ def test_nucleon_argument_errors(qdp):
     assert st == -6  # QDP_ERR_UNSUPPORTED
     for f in u:
         qdp.free(f)
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16S"])
+@pytest.mark.parametrize("dims", [(4, 6, 2, 4), (10, 6, 6, 2)])
+def test_delta_pp_two_point(qdp, prec, dims):
+    """Delta++ correlator (three u quarks, summed over mu = 1..3), both
+    parities, against the oracle's determinant form on the stored inputs."""
+    S = synth.gaussian_propagator(dims, 231)
+    lat = qdp.lattice(dims)
+    u = upload_cols(qdp, lat, S, prec)
+    Sr = np.stack([qdp.read(f) for f in u])
+    for parity in (1, -1):
+        ref = oracle.delta(Sr, dims, parity)
+        got = qdp.delta(u, parity=parity)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref)), parity
+    got = qdp.delta(u, parity=1, t0=1)
+    assert np.max(np.abs(np.roll(got, 1) - oracle.delta(Sr, dims, 1))) <= 1e-11 * np.max(np.abs(got))
+    for f in u:
+        qdp.free(f)
