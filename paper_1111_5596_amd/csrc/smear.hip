@@ -325,34 +325,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
     }
 }
 
-// Persistent multi-lattice kernel: a fixed grid walks a work list of
-// (lattice, tile) items; block b takes a contiguous run of items (XCD-aware
-// so one XCD's blocks share neighbouring tiles).
+// Persistent multi-lattice kernel: a grid of as many blocks as the chip
+// holds at once walks a work list of (lattice, tile) items, block b taking
+// items b, b + grid, b + 2 grid, ...  At every step the blocks in flight
+// work on one contiguous run of items (one XCD's blocks on one sub-run when
+// the mapping is XCD-aware), so neighbouring tiles are read while in L2, as
+// in a one-lattice launch.  A lattice's items alternate between its even
+// and its odd tiles: even tile k and odd tile k hold each other's
+// neighbours.
 template <int PREC, int OCC, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_batch_kernel(
-    const SmearJob* __restrict__ jobs,
-                                                          const int64_t* __restrict__ tile_start,
-                                                          int32_t njobs, SmearLaunch ln) {
+    const SmearJob* __restrict__ jobs, const int64_t* __restrict__ tile_start, int32_t njobs, SmearLaunch ln) {
     const int64_t ntiles = tile_start[njobs];
     int64_t b = blockIdx.x;
     if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
-    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    const int64_t t0 = b * per;
-    const int64_t t1 = min(ntiles, t0 + per);
     int j = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        while (j + 1 < njobs && tile_start[j + 1] <= t) ++j;  // tiles are ordered by job
-        if (t < tile_start[j]) {  // first tile of this run: binary search
-            int lo = 0, hi = njobs - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) / 2;
-                if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            j = lo;
-        }
+    for (int64_t t = b; t < ntiles; t += gridDim.x) {
+        while (j + 1 < njobs && tile_start[j + 1] <= t) ++j;  // items are ordered by lattice
         const SmearJob& job = jobs[j];
-        tile_update<PREC, BUF>(job, t - tile_start[j], 0, job.g.V, ln.site_waves, ln.col_groups,
-                          ln.kappa);
+        const int64_t u = t - tile_start[j];
+        tile_update<PREC, BUF>(job, u >> 1, (u & 1) * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups,
+                               ln.kappa);
     }
 }
 
@@ -815,9 +808,9 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
         h_first[j] = a;
         h_dst[j] = b;
         h_tmp[j] = c;
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 4; ++k) {  // an even and an odd tile per index
             const int64_t tile_sites = 64LL * (k + 1);
-            h_tiles[k * (njobs + 1) + j + 1] = h_tiles[k * (njobs + 1) + j] + (g.V + tile_sites - 1) / tile_sites;
+            h_tiles[k * (njobs + 1) + j + 1] = h_tiles[k * (njobs + 1) + j] + 2 * ((g.Vh + tile_sites - 1) / tile_sites);
         }
     }
     const size_t jb = sizeof(SmearJob) * njobs;
@@ -842,13 +835,18 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
         ln.xcd = sh.xcd;
         ln.kappa = kappa;
         const int64_t ntiles = h_tiles[k * (njobs + 1) + njobs];
-        int64_t grid = std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * 8);
-        grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
-        const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles) + k * (njobs + 1);
         Launch L;
         L.func = smear_func(prec, sh, true);
-        L.grid = dim3((unsigned)grid);
         L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
+        // as many blocks as are resident at once (a multiple of 8 for the XCD mapping)
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, L.func, (int)L.block.x, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        int64_t grid = std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * per_cu);
+        grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
+        const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles) + k * (njobs + 1);
+        L.grid = dim3((unsigned)grid);
         pack_args(L, reinterpret_cast<const SmearJob*>(J), T, njobs, ln);
         return L;
     };
