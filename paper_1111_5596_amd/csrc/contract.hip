@@ -118,6 +118,10 @@ struct RawCol<QDP_F16S> {
         const float2 f = f16s_decode(h[k], scale);
         return make_double2(f.x, f.y);
     }
+    // the stored half values without the record scale
+    __device__ __forceinline__ double2 stored(int k) const {
+        return make_double2((double)(float)h[k].x, (double)(float)h[k].y);
+    }
 };
 
 // One column at one site: 16-byte chunk loads (3 for F16S, 6 for F32, 12 for
@@ -200,11 +204,27 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
+                if constexpr (PREC == QDP_F16S) {
+                    // colour sums of the stored half values in FP64 (their
+                    // products are exact), then both record scales at once
+                    // (powers of two: an exact multiply)
+                    const double sc = (double)c2[b].scale * (double)c1[b].scale;
 #pragma unroll
-                for (int alpha = 0; alpha < 4; ++alpha)
+                    for (int alpha = 0; alpha < 4; ++alpha) {
+                        double2 part = make_double2(0.0, 0.0);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        cmac_conj(G[alpha], c2[b].at(3 * alpha + c), c1[b].at(3 * (alpha ^ SIGMA) + c));
+                        for (int c = 0; c < 3; ++c)
+                            cmac_conj(part, c2[b].stored(3 * alpha + c), c1[b].stored(3 * (alpha ^ SIGMA) + c));
+                        G[alpha].x = fmadd(sc, part.x, G[alpha].x);
+                        G[alpha].y = fmadd(sc, part.y, G[alpha].y);
+                    }
+                } else {
+#pragma unroll
+                    for (int alpha = 0; alpha < 4; ++alpha)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            cmac_conj(G[alpha], c2[b].at(3 * alpha + c), c1[b].at(3 * (alpha ^ SIGMA) + c));
+                }
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
