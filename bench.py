@@ -308,8 +308,8 @@ def main():
                          "instead of autotuning (for profiler runs that must repeat a measured shape)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the smearing would shard by time slices with no exchange; see DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the smearing would shard by whole time slices with no exchange)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -71,7 +71,7 @@ enum {
     QDP_ERR_LATTICE = -3,     /* fields on different lattices / bad extents */
     QDP_ERR_NOMEM = -4,       /* pool and spill area cannot hold the fields */
     QDP_ERR_ALIAS = -5,       /* destination aliases a shifted operand */
-    QDP_ERR_UNSUPPORTED = -6, /* valid request this build does not implement */
+    QDP_ERR_UNSUPPORTED = -6, /* valid request the library does not implement */
     QDP_ERR_HIP = -7,         /* HIP runtime error */
     QDP_ERR_STATE = -8        /* bad handle or context state */
 };
