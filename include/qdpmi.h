@@ -406,9 +406,12 @@ qdp_status qdp_fault_alloc_after(qdp_ctx* ctx, int64_t n);
  * that address until qdp_pool_free (it is never spilled or moved, and
  * qdp_set_pool_limit below its end fails with QDP_ERR_STATE).  Making room
  * may spill least-recently-used unpinned fields to pinned host memory (the
- * copies are enqueued on the context stream).  Errors: QDP_ERR_ARG (bytes 0,
- * null out), QDP_ERR_NOMEM (no room even with every field spilled; no
- * allocation is made, *out untouched). */
+ * copies are enqueued on the context stream).  The memory may still be read
+ * or written by work queued on the context stream (a spill copy, a freed
+ * field's last kernel): work on the context stream is ordered after it; a
+ * caller touching the block from another stream calls qdp_sync first.
+ * Errors: QDP_ERR_ARG (bytes 0, null out), QDP_ERR_NOMEM (no room even with
+ * every field spilled; no allocation is made, *out untouched). */
 qdp_status qdp_pool_malloc(qdp_ctx* ctx, size_t bytes, void** out);
 
 /* Return a block of qdp_pool_malloc to the pool.  The block may be reused by

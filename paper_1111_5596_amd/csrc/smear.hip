@@ -408,6 +408,8 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
             auto victim = ctx->graphs.begin();
             for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
                 if (g->second.last_use < victim->second.last_use) victim = g;
+            // the least recently used graph may still be running on the stream
+            QDP_HIP(ctx, hipStreamSynchronize(ctx->stream));
             hipGraphExecDestroy(victim->second.exec);
             ctx->graphs.erase(victim);
         }
