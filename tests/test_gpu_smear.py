@@ -159,6 +159,31 @@ def test_graph_replay_equals_eager(qdp):
         eager.close()
 
 
+def test_graph_cache_eviction(qdp):
+    """More distinct smearing calls than the graph cache holds (16): the least
+    recently used graphs are destroyed and rebuilt when needed again, and every
+    result equals the eager launches' bitwise."""
+    from paper_1111_5596_amd import qdpmi
+
+    dims = (4, 4, 2, 2)
+    U = synth.su3_links(dims, 6)
+    psi = synth.gaussian_propagator(dims, 106, ncols=20)
+    eager = qdpmi.Context(pool_bytes=1 << 28, flags=qdpmi.INIT_NO_GRAPH | qdpmi.INIT_NO_AUTOTUNE)
+    try:
+        res = []
+        for q in (qdp, eager):
+            lat, g, fs = upload(q, dims, U, psi, "F32")
+            for f in fs:  # 20 different argument sets: 20 graphs
+                q.smear(g, [f], 0.25, 3)
+            q.smear(g, [fs[0]], 0.25, 3)  # the first graph was evicted: rebuilt
+            res.append([q.read(f) for f in fs])
+            free_all(q, [g] + fs)
+        for a, b in zip(*res):
+            assert np.array_equal(a, b)
+    finally:
+        eager.close()
+
+
 def test_batch_equals_single_bitwise(qdp):
     sizes = [(4, 4, 4, 8), (6, 6, 6, 4), (8, 4, 4, 2), (4, 4, 4, 8)]
     jobs, single, expect = [], [], []
