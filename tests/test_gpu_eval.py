@@ -105,6 +105,57 @@ def test_eval_matches_oracle(env, idx, sub):
     q.free(d)
 
 
+@pytest.fixture(scope="module", params=["F32", "F16S"])
+def env_low(qdp, request):
+    """The same operands stored in FP32 or F16S; the oracle gets the stored
+    (rounded) values read back."""
+    prec = request.param
+    lat = qdp.lattice(DIMS)
+    host, handles = {}, {}
+    specs = {"psi": "FERMION", "chi": "FERMION", "A": "COLOR_MATRIX", "B": "COLOR_MATRIX",
+             "P": "PROPAGATOR", "Q": "PROPAGATOR", "M": "SPIN_MATRIX", "c": "COMPLEX",
+             "r": "REAL", "v": "COLOR_VECTOR", "w": "COLOR_VECTOR"}
+    for i, (k, t) in enumerate(specs.items()):
+        a = rand(SHAPES[t], 100 + i)
+        if t == "REAL":
+            a = a.real
+        h = qdp.alloc(lat, t, prec)
+        qdp.write(h, a)
+        host[k] = (t, qdp.read(h))
+        handles[k] = h
+    g = qdp.alloc(lat, "GAUGE", prec)
+    qdp.write(g, synth.su3_links(DIMS, 8))
+    host["U"] = ("GAUGE", qdp.read(g))
+    handles["U"] = g
+    yield qdp, lat, host, handles, prec
+    for h in handles.values():
+        qdp.free(h)
+
+
+@pytest.mark.parametrize("idx", range(len(PROGRAMS)))
+def test_eval_lower_precisions(env_low, idx):
+    """Every program with all operands and the destination in FP32 or F16S
+    storage (FP32 arithmetic): FP32 within 1e-5, F16S within 1e-3 of the
+    largest result (one F16S rounding of the stored result is 2^-12 of its
+    record's scale), on the full lattice and on the odd sites, whose
+    complement keeps its stored values bitwise."""
+    q, lat, host, handles, prec = env_low
+    t, prog = PROGRAMS[idx]
+    tol = {"F32": 1e-5, "F16S": 1e-3}[prec]
+    for sub in ("all", "odd"):
+        d = q.alloc(lat, t, prec)
+        dest0 = rand(SHAPES[t], 999)
+        q.write(d, dest0.real if t == "REAL" else dest0)
+        dest0 = q.read(d)
+        q.eval(to_gpu(prog, handles), d, sub)
+        expect = E.assign(prog, host, DIMS, t, dest0, sub)
+        got = q.read(d)
+        assert np.abs(got - expect).max() <= tol * max(1.0, np.abs(expect).max()), (prec, sub)
+        m = ~E.subset_mask(DIMS, sub)
+        assert np.array_equal(got[m], np.asarray(dest0)[m])
+        q.free(d)
+
+
 @pytest.mark.parametrize("op", ["+=", "-=", "*="])
 def test_compound_assign(env, op):
     q, lat, host, handles = env
