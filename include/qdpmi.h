@@ -458,17 +458,21 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
  * waves_per_simd selects the kernel variant compiled for that occupancy
  * (0, 2 or 3; 0 = compiler default; FP64 always uses 0), flat = 1 uses
  * 64-bit flat addresses instead of buffer addressing (forced on when a field
- * is 4 GiB or larger).  Every shape computes bitwise-identical results.
+ * is 4 GiB or larger), zstack = 1 gives the site_waves wavefronts of a
+ * block 64-site tiles one (x, y) plane apart (the tiles of z-neighbouring
+ * sites, so that the neighbour records they share are read by one CU;
+ * single-lattice launches with site_waves > 1, ignored otherwise) instead of
+ * consecutive tiles.  Every shape computes bitwise-identical results.
  * qdp_smear_set_shape forces a shape (site_waves = 0 returns to
  * autotuning); qdp_smear_get_shape reports the shape the last smearing call
- * used.  `reserved` must be 0. */
+ * used. */
 typedef struct {
     int32_t site_waves;
     int32_t col_groups;
     int32_t xcd;
     int32_t waves_per_simd;
     int32_t flat;
-    int32_t reserved;
+    int32_t zstack;
 } qdp_launch_shape;
 qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape);
 qdp_status qdp_smear_get_shape(qdp_ctx* ctx, qdp_launch_shape* out);

@@ -48,6 +48,8 @@ struct SmearLaunch {
     int32_t col_groups;  // column groups per site
     int32_t xcd;         // XCD-aware block mapping
     int32_t interleave;  // whole lattice: block 2b = even tile b, 2b+1 = odd tile b
+    int32_t zstride;     // > 0: the waves of a block take 64-site tiles zstride apart
+    int32_t pad;
     double kappa;
 };
 
@@ -288,16 +290,27 @@ __device__ __forceinline__ void site_update(const SmearJob& job, int32_t s, int 
     }
 }
 
-// Thread -> (site, column group) inside a tile of 64 * site_waves sites.
+// Thread -> (site, column group) for block `tile` of a range of sites.  The
+// site_waves wavefronts of a block take consecutive 64-site tiles, or, with
+// zstride > 0, tiles zstride apart: blocks p * zstride + r, r < zstride, cover
+// the group of site_waves * zstride tiles starting at tile p * site_waves *
+// zstride, wave w taking tile p * site_waves * zstride + w * zstride + r.
 template <int PREC, bool BUF>
 __device__ __forceinline__ void tile_update(const SmearJob& job, int64_t tile, int64_t site_begin,
-                                           int64_t site_count, int site_waves, int col_groups,
+                                           int64_t site_count, int site_waves, int col_groups, int zstride,
                                            double kappa) {
     // the wave index is uniform across the wavefront: keep it (and the
     // column range it selects) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int group = wave % col_groups, sw = wave / col_groups;
-    const int64_t local = (tile * site_waves + sw) * 64 + lane;
+    int64_t t64;
+    if (zstride > 0) {
+        const int64_t p = tile / zstride, r = tile - p * zstride;
+        t64 = (p * site_waves + sw) * zstride + r;
+    } else {
+        t64 = tile * site_waves + sw;
+    }
+    const int64_t local = t64 * 64 + lane;
     if (local >= site_count) return;
     const int cpt = (job.ncols + col_groups - 1) / col_groups;
     const int c0 = group * cpt;
@@ -319,9 +332,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
         // the even tile and the odd tile with the same index are each other's
         // neighbours: updating them together lets the L2 serve both
         const int64_t parity = b & 1;
-        tile_update<PREC, BUF>(job, b >> 1, parity * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups, ln.kappa);
+        tile_update<PREC, BUF>(job, b >> 1, parity * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups,
+                               ln.zstride, ln.kappa);
     } else {
-        tile_update<PREC, BUF>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.kappa);
+        tile_update<PREC, BUF>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.zstride,
+                               ln.kappa);
     }
 }
 
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
         while (j + 1 < njobs && tile_start[j + 1] <= t) ++j;  // items are ordered by lattice
         const SmearJob& job = jobs[j];
         const int64_t u = t - tile_start[j];
-        tile_update<PREC, BUF>(job, u >> 1, (u & 1) * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups,
+        tile_update<PREC, BUF>(job, u >> 1, (u & 1) * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups, 0,
                                ln.kappa);
     }
 }
@@ -484,10 +499,20 @@ Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t 
     SmearLaunch ln{};
     ln.site_begin = begin;
     ln.site_count = count;
-    const int64_t tile_sites = 64LL * sh.site_waves;
     ln.interleave = (begin == 0 && count == job.g.V) ? 1 : 0;
-    ln.nlogical = ln.interleave ? 2 * ((job.g.Vh + tile_sites - 1) / tile_sites)
-                                : (count + tile_sites - 1) / tile_sites;
+    // z-stacked blocks: one (x, y) plane of a parity, Lx/2 * Ly sites, in
+    // 64-site tiles (rounded)
+    ln.zstride = (sh.zstack && sh.site_waves > 1)
+                     ? (int32_t)std::max<int64_t>(1, ((int64_t)job.g.Lxh * job.g.L[1] + 32) / 64) : 0;
+    const int64_t range = ln.interleave ? job.g.Vh : count;  // sites of one parity's range
+    int64_t blocks;
+    if (ln.zstride > 0) {
+        const int64_t group = (int64_t)sh.site_waves * ln.zstride;
+        blocks = ((range + 63) / 64 + group - 1) / group * ln.zstride;
+    } else {
+        blocks = (range + 64LL * sh.site_waves - 1) / (64LL * sh.site_waves);
+    }
+    ln.nlogical = ln.interleave ? 2 * blocks : blocks;
     ln.site_waves = sh.site_waves;
     ln.col_groups = sh.col_groups;
     ln.xcd = sh.xcd;
@@ -595,20 +620,22 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
             for (int cg : groups) {
                 if (sw * cg > 4 || cg > job.ncols) continue;
                 for (int xcd : {0, 1})
-                    for (int occ : {0, 2, 3}) {
-                        if (prec == QDP_F64 && occ) continue;
-                        qdp_launch_shape sh{sw, cg, xcd, occ, flat, 0};
-                        float ms;
-                        QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));
-                        if (log)
-                            std::fprintf(stderr,
-                                         "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d: %.4f ms\n",
-                                         prec, job.ncols, (long long)count, sw, cg, xcd, occ, flat, ms);
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            best = sh;
+                    for (int occ : {0, 2, 3})
+                        for (int zs : {0, 1}) {
+                            if ((prec == QDP_F64 && occ) || (zs && sw == 1)) continue;
+                            qdp_launch_shape sh{sw, cg, xcd, occ, flat, zs};
+                            float ms;
+                            QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));
+                            if (log)
+                                std::fprintf(stderr,
+                                             "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d %d: "
+                                             "%.4f ms\n",
+                                             prec, job.ncols, (long long)count, sw, cg, xcd, occ, flat, zs, ms);
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                best = sh;
+                            }
                         }
-                    }
             }
     }
     ctx->tuned[key] = best;

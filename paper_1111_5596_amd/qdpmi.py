@@ -84,7 +84,7 @@ class qdp_cache_stats_t(ctypes.Structure):
 class qdp_launch_shape(ctypes.Structure):
     _fields_ = [("site_waves", ctypes.c_int32), ("col_groups", ctypes.c_int32),
                 ("xcd", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("flat", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flat", ctypes.c_int32), ("zstack", ctypes.c_int32)]
 
 
 _c = ctypes
@@ -412,15 +412,15 @@ class Context:
             raise ValueError("address outside the pool")
         return self._pool[off:off + nbytes]
 
-    def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0):
-        s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, 0)
+    def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0, zstack=0):
+        s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, zstack)
         self.check(lib.qdp_smear_set_shape(self.h, ctypes.byref(s)))
 
     def get_shape(self):
-        """(site_waves, col_groups, xcd, waves_per_simd, flat) of the last smearing call."""
+        """(site_waves, col_groups, xcd, waves_per_simd, flat, zstack) of the last smearing call."""
         s = qdp_launch_shape()
         self.check(lib.qdp_smear_get_shape(self.h, ctypes.byref(s)))
-        return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd, s.flat)
+        return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd, s.flat, s.zstack)
 
     def sync(self):
         self.check(lib.qdp_sync(self.h))

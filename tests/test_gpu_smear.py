@@ -117,8 +117,9 @@ def test_launch_shapes_bitwise(qdp, prec):
     out = qdp.alloc(lat, "FERMION", prec)
     ref = None
     try:
-        for shape in [(1, 1, 0, 0, 0), (4, 1, 1, 2, 0), (2, 2, 1, 3, 0), (1, 3, 0, 2, 1),
-                      (1, 4, 1, 0, 1), (2, 1, 0, 3, 1), (4, 1, 1, 2, 1)]:
+        for shape in [(1, 1, 0, 0, 0, 0), (4, 1, 1, 2, 0, 0), (2, 2, 1, 3, 0, 0), (1, 3, 0, 2, 1, 0),
+                      (1, 4, 1, 0, 1, 0), (2, 1, 0, 3, 1, 0), (4, 1, 1, 2, 1, 0), (2, 1, 1, 2, 0, 1),
+                      (4, 1, 0, 0, 1, 1), (2, 2, 1, 3, 0, 1)]:
             qdp.set_shape(*shape)
             outs = [qdp.alloc(lat, "FERMION", prec) for _ in fs]
             qdp.smear_to(g, fs, outs, 0.25, 5, mode=1)
@@ -127,7 +128,7 @@ def test_launch_shapes_bitwise(qdp, prec):
             if ref is None:
                 ref = vals
             for v, r in zip(vals, ref):
-                assert np.array_equal(v, r)
+                assert np.array_equal(v, r), shape
             free_all(qdp, outs)
     finally:
         qdp.set_shape(0)
@@ -136,6 +137,33 @@ def test_launch_shapes_bitwise(qdp, prec):
         if prec == "F32":
             assert np.array_equal(qdp.read(f), c.astype(np.complex64).astype(np.complex128))
     free_all(qdp, [g, out] + fs)
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 4, 4), (24, 12, 4, 2), (20, 20, 4, 2), (6, 6, 2, 2)])
+def test_zstacked_blocks_bitwise(qdp, dims):
+    """Blocks whose wavefronts take tiles one (x, y) plane apart, against
+    consecutive tiles, both modes: one parity's planes of 128, 144, 200 and
+    18 sites (tile strides 2, 2, 3 and 1) and tile groups that run past the
+    end of a parity (18 tiles per parity in groups of 8, 25 in groups of 12)."""
+    U = synth.su3_links(dims, 16)
+    psi = synth.gaussian_propagator(dims, 116, ncols=12)
+    lat, g, fs = upload(qdp, dims, U, psi, "F32")
+    try:
+        for mode in (0, 1):
+            ref = None
+            for shape in [(1, 1, 0, 0, 0, 0), (2, 1, 0, 2, 0, 1), (4, 1, 1, 0, 0, 1), (2, 2, 1, 3, 1, 1)]:
+                qdp.set_shape(*shape)
+                outs = [qdp.alloc(lat, "FERMION", "F32") for _ in fs]
+                qdp.smear_to(g, fs, outs, 0.25, 3, mode=mode)
+                vals = [qdp.read(o) for o in outs]
+                if ref is None:
+                    ref = vals
+                for v, r in zip(vals, ref):
+                    assert np.array_equal(v, r), (shape, mode)
+                free_all(qdp, outs)
+    finally:
+        qdp.set_shape(0)
+    free_all(qdp, [g] + fs)
 
 
 def test_graph_replay_equals_eager(qdp):
