@@ -446,24 +446,42 @@ __device__ __forceinline__ double2 pair_term(const double2 X[4][4], const double
     return make_double2(WD * f.x + WE * (a.x + b.x), WD * f.y + WE * (a.y + b.y));
 }
 
-// Kinds of baryon: the sink diquark matrix G (the source one follows), the
-// weights of the direct and exchange terms and the number of G summed.
-// Delta++: with three identical quarks the six Wick terms pair up (the
-// diquark tensors are antisymmetric under exchange of the two quarks they
-// hold) into twice the direct and four times the exchange term of the
-// proton form, with D = U.
+// Kinds of baryon: the sink diquark matrix G (the source one follows) and
+// the weights of the direct and exchange terms.  Delta++: with three
+// identical quarks the six Wick terms pair up (the diquark tensors are
+// antisymmetric under exchange of the two quarks they hold) into twice the
+// direct and four times the exchange term of the proton form, with D = U,
+// for each of G = C gamma_mu, mu = 1, 2, 3.  Every term is linear in
+// M = G D G', so the sum over mu is taken on M: one colour sum with
+// M = sum_mu G_mu D G'_mu.
 template <int KIND, int MU>
 struct BaryonKind {
     static constexpr SignedPerm G = KIND == QDP_BARYON_PROTON ? kCg5 : kCgamma[MU];
     static constexpr SignedPerm Gp = KIND == QDP_BARYON_PROTON ? sp_neg(kCg5) : source_diquark(kCgamma[MU]);
     static constexpr int WD = KIND == QDP_BARYON_PROTON ? 1 : 2;
     static constexpr int WE = KIND == QDP_BARYON_PROTON ? 1 : 4;
+    static constexpr int NMU = KIND == QDP_BARYON_PROTON ? 1 : 3;
 };
 
-// One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ].
-template <int PREC, bool BUF, int B, int BP, int KIND, int MU>
-__device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, double hp) {
+// M += G D G' with signed permutations:
+// M[r][G'.perm[q]] += i^(G.code[r] + G'.code[q]) D[G.perm[r]][q]
+template <int KIND, int MU>
+__device__ __forceinline__ void add_diquark(const double2 D[4][4], double2 M[4][4]) {
     using K = BaryonKind<KIND, MU>;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 z = times_ik(D[K::G.perm[r]][q], K::G.code[r] + K::Gp.code[q]);
+            M[r][K::Gp.perm[q]].x += z.x;
+            M[r][K::Gp.perm[q]].y += z.y;
+        }
+}
+
+// One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ].
+template <int PREC, bool BUF, int B, int BP, int KIND>
+__device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, double hp) {
+    using K = BaryonKind<KIND, 0>;
     constexpr int X0 = B == 0 ? 1 : 0, Y0 = B == 2 ? 1 : 2;
     constexpr int XP = BP == 0 ? 1 : 0, YP = BP == 2 ? 1 : 2;
     // (x, b, y) is an even permutation of (0, 1, 2) only for b = 1
@@ -472,13 +490,13 @@ __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, d
     {
         double2 D[4][4];
         load_block<PREC, BUF, B, BP>(A.sd, s, D);
-        // M = G D G' with signed permutations:
-        // M[r][G'.perm[q]] = i^(G.code[r] + G'.code[q]) D[G.perm[r]][q]
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                M[r][K::Gp.perm[q]] = times_ik(D[K::G.perm[r]][q], K::G.code[r] + K::Gp.code[q]);
+            for (int q = 0; q < 4; ++q) M[r][q] = make_double2(0.0, 0.0);
+        add_diquark<KIND, 0>(D, M);
+        if constexpr (K::NMU > 1) add_diquark<KIND, 1>(D, M);
+        if constexpr (K::NMU > 2) add_diquark<KIND, 2>(D, M);
     }
     double2 X[4][4], Y[4][4];
     load_block<PREC, BUF, X0, XP>(A.su, s, X);
@@ -490,7 +508,7 @@ __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, d
     return make_double2(SG * (f1.x - f2.x), SG * (f1.y - f2.y));
 }
 
-template <int PREC, bool BUF, int KIND, int MU>
+template <int PREC, bool BUF, int KIND>
 __device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, double hp) {
     double2 acc = make_double2(0.0, 0.0);
     // the nine colour steps run one after another (a runtime loop, so the
@@ -499,15 +517,15 @@ __device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, do
     for (int bb = 0; bb < 9; ++bb) {
         double2 d;
         switch (__builtin_amdgcn_readfirstlane(bb)) {
-            case 0: d = colour_step<PREC, BUF, 0, 0, KIND, MU>(A, s, hp); break;
-            case 1: d = colour_step<PREC, BUF, 0, 1, KIND, MU>(A, s, hp); break;
-            case 2: d = colour_step<PREC, BUF, 0, 2, KIND, MU>(A, s, hp); break;
-            case 3: d = colour_step<PREC, BUF, 1, 0, KIND, MU>(A, s, hp); break;
-            case 4: d = colour_step<PREC, BUF, 1, 1, KIND, MU>(A, s, hp); break;
-            case 5: d = colour_step<PREC, BUF, 1, 2, KIND, MU>(A, s, hp); break;
-            case 6: d = colour_step<PREC, BUF, 2, 0, KIND, MU>(A, s, hp); break;
-            case 7: d = colour_step<PREC, BUF, 2, 1, KIND, MU>(A, s, hp); break;
-            default: d = colour_step<PREC, BUF, 2, 2, KIND, MU>(A, s, hp); break;
+            case 0: d = colour_step<PREC, BUF, 0, 0, KIND>(A, s, hp); break;
+            case 1: d = colour_step<PREC, BUF, 0, 1, KIND>(A, s, hp); break;
+            case 2: d = colour_step<PREC, BUF, 0, 2, KIND>(A, s, hp); break;
+            case 3: d = colour_step<PREC, BUF, 1, 0, KIND>(A, s, hp); break;
+            case 4: d = colour_step<PREC, BUF, 1, 1, KIND>(A, s, hp); break;
+            case 5: d = colour_step<PREC, BUF, 1, 2, KIND>(A, s, hp); break;
+            case 6: d = colour_step<PREC, BUF, 2, 0, KIND>(A, s, hp); break;
+            case 7: d = colour_step<PREC, BUF, 2, 1, KIND>(A, s, hp); break;
+            default: d = colour_step<PREC, BUF, 2, 2, KIND>(A, s, hp); break;
         }
         acc.x += d.x;
         acc.y += d.y;
@@ -526,18 +544,9 @@ __global__ __launch_bounds__(256) void baryon_kernel(BaryonArgs A) {
     for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
-        if constexpr (KIND == QDP_BARYON_PROTON) {
-            const double2 d = colour_sum<PREC, BUF, KIND, 0>(A, s, hp);
-            acc.x += d.x;
-            acc.y += d.y;
-        } else {
-            // sum over the spatial mu = 1, 2, 3
-            const double2 d1 = colour_sum<PREC, BUF, KIND, 0>(A, s, hp);
-            const double2 d2 = colour_sum<PREC, BUF, KIND, 1>(A, s, hp);
-            const double2 d3 = colour_sum<PREC, BUF, KIND, 2>(A, s, hp);
-            acc.x += (d1.x + d2.x) + d3.x;
-            acc.y += (d1.y + d2.y) + d3.y;
-        }
+        const double2 d = colour_sum<PREC, BUF, KIND>(A, s, hp);
+        acc.x += d.x;
+        acc.y += d.y;
     }
     __shared__ double red[4][2];
     const double re = wave_sum(acc.x), im = wave_sum(acc.y);
