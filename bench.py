@@ -245,10 +245,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(shape=None):
     """HBM bytes per launch of the profiled kernel (rocprofv3 FETCH_SIZE +
     WRITE_SIZE, scaled by the copy-kernel calibration), if the committed
-    measurement was taken on the current kernel sources; else None."""
+    measurement was taken on the current kernel sources and, when `shape` is
+    given, with that launch shape; else None."""
     path = os.path.join(ROOT, "profiles", "smear_f16s_48c96_traffic.txt")
     rec = {}
     try:
@@ -260,6 +261,8 @@ def measured_traffic():
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    if shape is not None and rec.get("launch_shape_tuple") != ",".join(str(int(x)) for x in shape):
         return None
     try:
         return float(rec["traffic_bytes_per_launch"])
@@ -355,7 +358,7 @@ def main():
     per_launch_units = 12 * V // 2  # site-updates of one checkerboard pass
     model_bytes = MODEL_BYTES_PER_SITE_UPDATE[("F16S", True)] * per_launch_units
     achieved = model_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(f16["shape"])
     out = {
         "metric": "smearing site-updates/s + achieved HBM GB/s; batched/mixed vs plain FP32",
         "value": value,

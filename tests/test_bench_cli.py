@@ -44,3 +44,9 @@ def test_traffic_record_parses_and_is_keyed_to_the_kernel():
     assert len(rec["kernel_source_sha256"]) == 64
     # the record is reported only while it matches the kernel sources
     assert (bench.measured_traffic() is None) == (rec["kernel_source_sha256"] != bench.kernel_source_digest())
+    # and only for the launch shape it was measured with
+    shape = tuple(int(x) for x in rec["launch_shape_tuple"].split(","))
+    assert len(shape) == 6
+    assert (bench.measured_traffic(shape) is None) == (bench.measured_traffic() is None)
+    other = (shape[0] % 4 + 1,) + shape[1:]
+    assert bench.measured_traffic(other) is None
