@@ -383,7 +383,8 @@ def main():
                      "bytes_per_launch": model_bytes, "units_per_launch": per_launch_units,
                      "bytes_per_unit": MODEL_BYTES_PER_SITE_UPDATE[("F16S", True)], "launch_ms": launch_ms,
                      "pass_minimum_bytes_per_launch": pass_bytes(V, "F16S", True),
-                     "pass_minimum_GBps": pass_bytes(V, "F16S", True) / (launch_ms * 1e-3) / 1e9},
+                     "pass_minimum_GBps": pass_bytes(V, "F16S", True) / (launch_ms * 1e-3) / 1e9,
+                     "pass_minimum_frac": pass_bytes(V, "F16S", True) / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS},
         "smear_ms_per_step": f16["smear_ms"],
         "contract_ms_per_step": f16["contract_ms"],
         "smear_site_updates_per_s": site_updates / (f16["smear_ms"] * 1e-3),
