@@ -170,6 +170,15 @@ struct FieldRef {
         else
             *reinterpret_cast<T*>(const_cast<char*>(base) + so + (int64_t)row * 64 * (int64_t)sizeof(T)) = v;
     }
+    // non-temporal store of a 4-byte value (see ChunkRef::store_stream)
+    __device__ __forceinline__ void store_stream(T v, int row, int64_t so) const {
+        static_assert(sizeof(T) == 4, "4-byte rows only");
+        if constexpr (BUF)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rsrc, (int)(uint32_t)so,
+                                                  row * 64 * 4, 2);
+        else
+            __builtin_nontemporal_store(v, reinterpret_cast<T*>(const_cast<char*>(base) + so + (int64_t)row * 64 * 4));
+    }
 };
 
 // Access to the 16-byte chunks of a chunked field (see common.hpp): `so16` is
@@ -194,6 +203,15 @@ struct ChunkRef {
         else
             *reinterpret_cast<u32x4_t*>(const_cast<char*>(base) + so16 + (int64_t)q * 1024) = v;
     }
+    // non-temporal store (cache policy nt): for results the kernel never
+    // reads back, so that they do not push the records it still reads out
+    // of the caches
+    __device__ __forceinline__ void store_stream(u32x4_t v, int q, int64_t so16) const {
+        if constexpr (BUF)
+            __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, (int)(uint32_t)so16, q * 1024, 2);
+        else
+            __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t*>(const_cast<char*>(base) + so16 + (int64_t)q * 1024));
+    }
 };
 
 template <typename T2>
@@ -217,8 +235,9 @@ __device__ __forceinline__ void load_elems(const ChunkRef<BUF>& f, int64_t so16,
     }
 }
 
-// Store elements [0, N) of a site, N a multiple of the chunk size.
-template <int N, typename T2, bool BUF>
+// Store elements [0, N) of a site, N a multiple of the chunk size
+// (STREAM: non-temporal stores).
+template <int N, bool STREAM = false, typename T2, bool BUF>
 __device__ __forceinline__ void store_elems(const ChunkRef<BUF>& f, int64_t so16, const T2* in) {
     constexpr int CE = 16 / sizeof(T2);
     static_assert(N % CE == 0, "whole chunks only");
@@ -227,7 +246,10 @@ __device__ __forceinline__ void store_elems(const ChunkRef<BUF>& f, int64_t so16
         Chunk<T2> c;
 #pragma unroll
         for (int j = 0; j < CE; ++j) c.v[j] = in[q * CE + j];
-        f.store(__builtin_bit_cast(u32x4_t, c), q, so16);
+        if constexpr (STREAM)
+            f.store_stream(__builtin_bit_cast(u32x4_t, c), q, so16);
+        else
+            f.store(__builtin_bit_cast(u32x4_t, c), q, so16);
     }
 }
 

@@ -138,7 +138,7 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
             out[k].x = fmadd(kappa, acc[k].x, out[k].x);
             out[k].y = fmadd(kappa, acc[k].y, out[k].y);
         }
-        store_elems<12>(ChunkRef<BUF>(job.dst[c]), cs, out);
+        store_elems<12, true>(ChunkRef<BUF>(job.dst[c]), cs, out);
     }
 }
 
@@ -273,8 +273,8 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
         half2_t q[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) q[k] = f16s_encode(out[k].x, out[k].y, e);
-        store_elems<12>(ChunkRef<BUF>(job.dst[c]), cs, q);
-        FieldRef<float, BUF>(job.dst[c]).store(m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f, 12, cs4);
+        store_elems<12, true>(ChunkRef<BUF>(job.dst[c]), cs, q);
+        FieldRef<float, BUF>(job.dst[c]).store_stream(m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f, 12, cs4);
     }
 }
 
