@@ -197,6 +197,13 @@ struct ChunkRef {
         else
             return *reinterpret_cast<const u32x4_t*>(base + so16 + (int64_t)q * 1024);
     }
+    // non-temporal load (cache policy nt): for data read once
+    __device__ __forceinline__ u32x4_t load_stream(int q, int64_t so16) const {
+        if constexpr (BUF)
+            return __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(uint32_t)so16, q * 1024, 2);
+        else
+            return __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(base + so16 + (int64_t)q * 1024));
+    }
     __device__ __forceinline__ void store(u32x4_t v, int q, int64_t so16) const {
         if constexpr (BUF)
             __builtin_amdgcn_raw_buffer_store_b128(v, rsrc, (int)(uint32_t)so16, q * 1024, 0);
@@ -221,12 +228,12 @@ struct Chunk {
 
 // Complex elements [E0, E0 + N) of a site of a chunked field (element e lies
 // in chunk e / (16 / sizeof(T2))), one 16-byte load per chunk touched.
-template <int E0, int N, typename T2, bool BUF>
+template <int E0, int N, bool STREAM = false, typename T2, bool BUF>
 __device__ __forceinline__ void load_elems(const ChunkRef<BUF>& f, int64_t so16, T2* out) {
     constexpr int CE = 16 / sizeof(T2);
 #pragma unroll
     for (int q = E0 / CE; q <= (E0 + N - 1) / CE; ++q) {
-        const Chunk<T2> c = __builtin_bit_cast(Chunk<T2>, f.load(q, so16));
+        const Chunk<T2> c = __builtin_bit_cast(Chunk<T2>, STREAM ? f.load_stream(q, so16) : f.load(q, so16));
 #pragma unroll
         for (int j = 0; j < CE; ++j) {
             const int e = q * CE + j;

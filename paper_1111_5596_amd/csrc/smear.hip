@@ -121,7 +121,7 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
         T2 own[12];
 #pragma unroll
         for (int i = 0; i < 3; ++i) load_elems<0, 12>(src, cb[i], v[i]);
-        load_elems<0, 12>(src, cs, own);
+        load_elems<0, 12, true>(src, cs, own);  // read once: non-temporal
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -213,7 +213,7 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
             vsc[2 * i] = ssc.load(12, cf4[i]);
             vsc[2 * i + 1] = ssc.load(12, cb4[i]);
         }
-        load_elems<0, 12>(src, cs, own);
+        load_elems<0, 12, true>(src, cs, own);  // read once: non-temporal
         so = ssc.load(12, cs4);
         __builtin_amdgcn_sched_barrier(0);
 
