@@ -454,7 +454,10 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
 
 /* Launch shape of the smearing kernel: sites per block = 64 * site_waves,
  * column groups = col_groups (each thread updates ceil(ncols / col_groups)
- * columns of one site), xcd = 1 maps consecutive blocks to one XCD,
+ * columns of one site), xcd = 1 maps consecutive blocks to one XCD, xcd =
+ * 2 keeps each z-stack group of blocks on one XCD with the eight XCDs on
+ * adjacent groups (z-stacked shapes; the multi-lattice kernel treats it as
+ * 1),
  * waves_per_simd selects the kernel variant compiled for that occupancy
  * (0, 2 or 3; 0 = compiler default; FP64 always uses 0), flat = 1 uses
  * 64-bit flat addresses instead of buffer addressing (forced on when a field

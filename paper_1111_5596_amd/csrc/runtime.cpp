@@ -609,7 +609,7 @@ qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape) {
     if (!ctx || !shape) return set_error(ctx, QDP_ERR_ARG, "null argument");
     if (shape->site_waves != 0) {
         const int sw = shape->site_waves, cg = shape->col_groups;
-        if (sw < 1 || cg < 1 || cg > 12 || sw * cg > 4 || shape->xcd < 0 || shape->xcd > 1 ||
+        if (sw < 1 || cg < 1 || cg > 12 || sw * cg > 4 || shape->xcd < 0 || shape->xcd > 2 ||
             !(shape->waves_per_simd == 0 || shape->waves_per_simd == 2 || shape->waves_per_simd == 3) ||
             shape->flat < 0 || shape->flat > 1 || shape->zstack < 0 || shape->zstack > 1)
             return set_error(ctx, QDP_ERR_ARG, "launch shape out of range (site_waves * col_groups <= 4)");

@@ -49,7 +49,7 @@ struct SmearLaunch {
     int32_t xcd;         // XCD-aware block mapping
     int32_t interleave;  // whole lattice: block 2b = even tile b, 2b+1 = odd tile b
     int32_t zstride;     // > 0: the waves of a block take 64-site tiles zstride apart
-    int32_t pad;
+    int32_t xcd_group;   // xcd = 2: logical blocks per group kept on one XCD
     double kappa;
 };
 
@@ -326,7 +326,15 @@ template <int PREC, int OCC, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_kernel(
     SmearJob job, SmearLaunch ln) {
     int64_t b = blockIdx.x;
-    if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
+    if (ln.xcd == 1) {
+        b = xcd_logical_block(b, gridDim.x);
+    } else if (ln.xcd == 2) {
+        // groups of xcd_group consecutive logical blocks each on one XCD
+        // (blocks are dispatched to the XCDs in turn): XCD x takes groups
+        // x, x + 8, x + 16, ..., so the eight groups in flight are adjacent
+        const int64_t x = b & 7, j = b >> 3;
+        b = (x + 8 * (j / ln.xcd_group)) * ln.xcd_group + j % ln.xcd_group;
+    }
     if (b >= ln.nlogical) return;
     if (ln.interleave) {
         // the even tile and the odd tile with the same index are each other's
@@ -518,7 +526,15 @@ Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t 
     ln.xcd = sh.xcd;
     ln.kappa = kappa;
     int64_t grid = ln.nlogical;
-    if (sh.xcd) grid = (grid + 7) / 8 * 8;
+    if (sh.xcd == 1) {
+        grid = (grid + 7) / 8 * 8;
+    } else if (sh.xcd == 2) {
+        // a group: the blocks of one z-stack group (both parities' in the
+        // interleaved launch), or 8 blocks without z-stacking
+        ln.xcd_group = ln.zstride > 0 ? (ln.interleave ? 2 : 1) * ln.zstride : 8;
+        const int64_t unit = 8LL * ln.xcd_group;
+        grid = (grid + unit - 1) / unit * unit;
+    }
     Launch L;
     L.func = smear_func(prec, sh, false);
     L.grid = dim3((unsigned)grid);
@@ -623,10 +639,10 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
         for (int sw : {1, 2, 4})
             for (int cg : groups) {
                 if (sw * cg > 4 || cg > job.ncols) continue;
-                for (int xcd : {0, 1})
+                for (int xcd : {0, 1, 2})
                     for (int occ : {0, 2, 3})
                         for (int zs : {0, 1}) {
-                            if ((prec == QDP_F64 && occ) || (zs && sw == 1)) continue;
+                            if ((prec == QDP_F64 && occ) || (zs && sw == 1) || (xcd == 2 && !zs)) continue;
                             qdp_launch_shape sh{sw, cg, xcd, occ, flat, zs};
                             float ms;
                             QDP_CHECK(time_shape(ctx, prec, job, begin, count, sh, kappa, &ms));

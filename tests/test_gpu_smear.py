@@ -119,7 +119,7 @@ def test_launch_shapes_bitwise(qdp, prec):
     try:
         for shape in [(1, 1, 0, 0, 0, 0), (4, 1, 1, 2, 0, 0), (2, 2, 1, 3, 0, 0), (1, 3, 0, 2, 1, 0),
                       (1, 4, 1, 0, 1, 0), (2, 1, 0, 3, 1, 0), (4, 1, 1, 2, 1, 0), (2, 1, 1, 2, 0, 1),
-                      (4, 1, 0, 0, 1, 1), (2, 2, 1, 3, 0, 1)]:
+                      (4, 1, 0, 0, 1, 1), (2, 2, 1, 3, 0, 1), (4, 1, 2, 0, 0, 1), (2, 2, 2, 2, 1, 1)]:
             qdp.set_shape(*shape)
             outs = [qdp.alloc(lat, "FERMION", prec) for _ in fs]
             qdp.smear_to(g, fs, outs, 0.25, 5, mode=1)
@@ -151,7 +151,8 @@ def test_zstacked_blocks_bitwise(qdp, dims):
     try:
         for mode in (0, 1):
             ref = None
-            for shape in [(1, 1, 0, 0, 0, 0), (2, 1, 0, 2, 0, 1), (4, 1, 1, 0, 0, 1), (2, 2, 1, 3, 1, 1)]:
+            for shape in [(1, 1, 0, 0, 0, 0), (2, 1, 0, 2, 0, 1), (4, 1, 1, 0, 0, 1), (2, 2, 1, 3, 1, 1),
+                          (4, 1, 2, 2, 0, 1), (2, 1, 2, 0, 1, 1)]:
                 qdp.set_shape(*shape)
                 outs = [qdp.alloc(lat, "FERMION", "F32") for _ in fs]
                 qdp.smear_to(g, fs, outs, 0.25, 3, mode=mode)
