@@ -245,29 +245,42 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(shape=None):
-    """HBM bytes per launch of the profiled kernel (rocprofv3 FETCH_SIZE +
-    WRITE_SIZE, scaled by the copy-kernel calibration), if the committed
-    measurement was taken on the current kernel sources and, when `shape` is
-    given, with that launch shape; else None."""
-    path = os.path.join(ROOT, "profiles", "smear_f16s_48c96_traffic.txt")
-    rec = {}
-    try:
+def traffic_records():
+    """The committed traffic records (profiles/smear_f16s_48c96_traffic*.txt,
+    one per profiled launch shape, the first the shape of the profiled
+    benchmark run) as dicts of their `key: value` lines."""
+    import glob
+
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "smear_f16s_48c96_traffic*.txt")),
+                   key=lambda p: (not p.endswith("_traffic.txt"), p))
+    recs = []
+    for path in paths:
+        rec = {}
         with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     rec[k.strip()] = v.strip()
-    except OSError:
-        return None
-    if rec.get("kernel_source_sha256") != kernel_source_digest():
-        return None
-    if shape is not None and rec.get("launch_shape_tuple") != ",".join(str(int(x)) for x in shape):
-        return None
-    try:
-        return float(rec["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        recs.append(rec)
+    return recs
+
+
+def measured_traffic(shape=None):
+    """HBM bytes per launch of the profiled kernel (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel calibration) from a record taken on
+    the current kernel sources and, when `shape` is given, with that launch
+    shape; else None."""
+    want = None if shape is None else ",".join(str(int(x)) for x in shape)
+    for rec in traffic_records():
+        if rec.get("kernel_source_sha256") != kernel_source_digest():
+            continue
+        if want is not None and rec.get("launch_shape_tuple") != want:
+            continue
+        try:
+            return float(rec["traffic_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def cpu_baseline(full_steps_niter=NITER):

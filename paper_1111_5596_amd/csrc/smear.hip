@@ -597,7 +597,7 @@ qdp_status time_shape(Ctx* ctx, int prec, const SmearJob& job, int64_t begin, in
     QDP_HIP(ctx, hipEventCreate(&e0));
     QDP_HIP(ctx, hipEventCreate(&e1));
     float best = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 5; ++rep) {
         hipEventRecord(e0, ctx->stream);
         hipLaunchKernel(L.func, L.grid, L.block, p.data(), 0, ctx->stream);
         hipEventRecord(e1, ctx->stream);
