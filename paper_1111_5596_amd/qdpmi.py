@@ -413,6 +413,10 @@ class Context:
         return self._pool[off:off + nbytes]
 
     def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0, zstack=0):
+        """Force the smearing launch shape (qdp_smear_set_shape; site_waves = 0
+        returns to autotuning).  xcd: 0 blocks dealt to the XCDs in turn, 1
+        consecutive blocks on one XCD, 2 z-stack groups on one XCD; zstack: the
+        waves of a block take tiles one (x, y) plane apart."""
         s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, zstack)
         self.check(lib.qdp_smear_set_shape(self.h, ctypes.byref(s)))
 
