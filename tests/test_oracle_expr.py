@@ -143,12 +143,114 @@ def test_gamma_products():
         eps = (-1) ** (k * (k - 1) // 2)
         _, got = ev([("field", "psi"), ("gamma_left", n), ("gamma_left", n)], f)
         assert np.allclose(got, eps * f["psi"][1], atol=1e-14)
-        _, l = ev([("field", "P"), ("gamma_left", n)], f)
-        assert np.allclose(l, np.einsum("ij,vjkab->vikab", oracle.gamma(n), f["P"][1]))
-        _, r = ev([("field", "P"), ("gamma_right", n)], f)
-        assert np.allclose(r, np.einsum("vijab,jk->vikab", f["P"][1], oracle.gamma(n)))
 
 
+# DeGrand-Rossi gamma_1..gamma_4 written out as dense matrices, independent of
+# the oracle's tables; Gamma_n = gamma_1^b0 gamma_2^b1 gamma_3^b2 gamma_4^b3
+# for the bits b_k of n.
+_DR = [np.array(m, dtype=np.complex128) for m in (
+    [[0, 0, 0, 1j], [0, 0, 1j, 0], [0, -1j, 0, 0], [-1j, 0, 0, 0]],
+    [[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]],
+    [[0, 0, 1j, 0], [0, 0, 0, -1j], [-1j, 0, 0, 0], [0, 1j, 0, 0]],
+    [[0, 0, 1, 0], [0, 0, 0, 1], [1, 0, 0, 0], [0, 1, 0, 0]])]
+
+
+def _gamma_written_out(n):
+    g = np.eye(4, dtype=np.complex128)
+    for k in range(4):
+        if (n >> k) & 1:
+            g = g @ _DR[k]
+    return g
+
+
+def _basis_fields(dims):
+    """Every spin basis element at its own site: SPIN_MATRIX E_{ij} at site
+    4 i + j and FERMION e_{s,a} (spin s, colour a) at site 3 s + a; zero
+    elsewhere.  Applying a 4x4 matrix G to them reads G off entry by entry."""
+    V = synth.volume(dims)
+    assert V >= 16
+    M = np.zeros((V, 4, 4), dtype=np.complex128)
+    psi = np.zeros((V, 4, 3), dtype=np.complex128)
+    for i in range(4):
+        for j in range(4):
+            M[4 * i + j, i, j] = 1.0
+    for s in range(4):
+        for a in range(3):
+            psi[3 * s + a, s, a] = 1.0
+    return M, psi
+
+
+@pytest.mark.parametrize("n", range(16))
+def test_gamma_left_right_match_written_out_products(n):
+    """gamma_left(n) a = Gamma_n a and gamma_right(n) a = a Gamma_n on basis
+    fields, Gamma_n built here from the written-out gamma_1..gamma_4 in the
+    order gamma_1^b0 gamma_2^b1 gamma_3^b2 gamma_4^b3.  The transpose, the
+    adjoint or the reversed product of Gamma_n fails for some n (checked
+    below), so each entry of the operation is pinned."""
+    G = _gamma_written_out(n)
+    M, psi = _basis_fields(DIMS)
+    f = {"M": ("SPIN_MATRIX", M), "psi": ("FERMION", psi)}
+    _, gl = ev([("field", "M"), ("gamma_left", n)], f)
+    _, gr = ev([("field", "M"), ("gamma_right", n)], f)
+    _, gp = ev([("field", "psi"), ("gamma_left", n)], f)
+    for i in range(4):
+        for j in range(4):
+            E_ij = np.zeros((4, 4))
+            E_ij[i, j] = 1.0
+            assert np.array_equal(gl[4 * i + j], G @ E_ij)
+            assert np.array_equal(gr[4 * i + j], E_ij @ G)
+    for s in range(4):
+        for a in range(3):
+            # Gamma e_{s,a}: column s of Gamma in colour a
+            expect = np.zeros((4, 3), dtype=np.complex128)
+            expect[:, a] = G[:, s]
+            assert np.array_equal(gp[3 * s + a], expect)
+    assert not np.any(gl[16:]) and not np.any(gp[12:])
+
+
+def test_gamma_written_out_products_discriminate():
+    """The pins above would catch the plausible mistakes: for some n the
+    transpose, the adjoint and the reversed-order product all differ from
+    Gamma_n."""
+    def reversed_product(n):
+        g = np.eye(4, dtype=np.complex128)
+        for k in reversed(range(4)):
+            if (n >> k) & 1:
+                g = g @ _DR[k]
+        return g
+
+    G = [_gamma_written_out(n) for n in range(16)]
+    assert any(not np.allclose(g, g.T) for g in G)
+    assert any(not np.allclose(g, g.conj().T) for g in G)
+    assert any(not np.allclose(G[n], reversed_product(n)) for n in range(16))
+    # gamma_5 = Gamma_15 = diag(1, 1, -1, -1) in this basis
+    assert np.allclose(G[15], np.diag([1, 1, -1, -1]))
+
+
+def _propagator_from_columns(S):
+    """12 FERMION columns (12, V, 4, 3) -> PROPAGATOR (V, 4, 4, 3, 3) with
+    P[x, s, s', a, a'] = component (s, a) of column 3 s' + a'."""
+    V = S.shape[1]
+    return np.transpose(S.reshape(4, 3, V, 4, 3), (2, 3, 0, 4, 1))
+
+
+def test_meson_from_expression_programs_matches_contraction():
+    """C_n(t) = sum_{x in t} Tr[gamma_5 S2^dagger gamma_5 Gamma_n S1 Gamma_n]
+    written as an expression program (gamma_left / gamma_right, adj, product,
+    trace, time-slice sum) equals the C oracle's contraction on a 2^4 lattice
+    for every n: the expression operations and the contraction are two
+    independent codings of the same formula."""
+    dims = (2, 2, 2, 2)
+    S1 = synth.gaussian_propagator(dims, 211)
+    S2 = synth.gaussian_propagator(dims, 212)
+    f = {"S1": ("PROPAGATOR", _propagator_from_columns(S1)),
+         "S2": ("PROPAGATOR", _propagator_from_columns(S2))}
+    ref = oracle.meson(S1, S2, dims)
+    for n in range(16):
+        prog = [("field", "S2"), ("adj",), ("gamma_left", 15), ("gamma_right", 15),
+                ("field", "S1"), ("gamma_left", n), ("gamma_right", n), ("mul",), ("trace",)]
+        _, got = E.sum_multi(prog, f, dims, "timeslice")
+        assert np.abs(got[:, 0] - ref[n]).max() <= 1e-13 * np.abs(ref[15]).max(), n
 def test_local_norm_and_inner():
     f = fields()
     t, n2 = ev([("field", "psi"), ("local_norm2",)], f)
