@@ -162,6 +162,15 @@ def _u64_array(handles):
     return (ctypes.c_uint64 * len(handles))(*[int(h) for h in handles])
 
 
+def _propagator(handles, name):
+    """The 12 column handles of a propagator as a ctypes array: the C side
+    reads exactly 12, so a shorter or longer list is refused here."""
+    hs = list(handles)
+    if len(hs) != 12:
+        raise ValueError(f"{name}: a propagator is 12 column handles, got {len(hs)}")
+    return _u64_array(hs)
+
+
 class Expr:
     """Postfix program for qdp_eval / qdp_sum_multi built from the same tuple
     form the tests use: ('field', handle), ('gauge', handle, mu), ('mul',) ..."""
@@ -333,39 +342,43 @@ class Context:
         self.check(lib.qdp_smear_jacobi_batch(self.h, arr, len(jobs), kappa, n_iter))
 
     def contract(self, S1, S2, mask=0xFFFF, t0=0, j_decay=3):
+        a, b = _propagator(S1, "contract S1"), _propagator(S2, "contract S2")
         lat = self.field_meta[S1[0]][0]
         Lt = self.lattice_dims[lat][3]
         out = np.zeros(16 * Lt * 2, dtype=np.float64)
-        self.check(lib.qdp_hadron_contract(self.h, _u64_array(S1), _u64_array(S2), mask, t0, j_decay,
+        self.check(lib.qdp_hadron_contract(self.h, a, b, mask, t0, j_decay,
                                            out.ctypes.data_as(_dp)))
         return out.view(np.complex128).reshape(16, Lt)
 
     def contract_mom(self, S1, S2, moms, mask=0xFFFF, t0=0, j_decay=3):
         """C_n(p, t), shape (nmom, 16, Lt), for integer momenta `moms`."""
+        a, b = _propagator(S1, "contract_mom S1"), _propagator(S2, "contract_mom S2")
         lat = self.field_meta[S1[0]][0]
         Lt = self.lattice_dims[lat][3]
         k = np.ascontiguousarray(np.asarray(moms, dtype=np.int32).reshape(-1, 3))
         out = np.zeros(k.shape[0] * 16 * Lt * 2, dtype=np.float64)
-        self.check(lib.qdp_hadron_contract_mom(self.h, _u64_array(S1), _u64_array(S2), mask,
+        self.check(lib.qdp_hadron_contract_mom(self.h, a, b, mask,
                                                k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), k.shape[0],
                                                t0, j_decay, out.ctypes.data_as(_dp)))
         return out.view(np.complex128).reshape(k.shape[0], 16, Lt)
 
     def nucleon(self, Su, Sd, parity=1, t0=0, j_decay=3):
         """Proton two-point function C(t), shape (Lt,) complex."""
+        a, b = _propagator(Su, "nucleon Su"), _propagator(Sd, "nucleon Sd")
         lat = self.field_meta[Su[0]][0]
         Lt = self.lattice_dims[lat][3]
         out = np.zeros(Lt * 2, dtype=np.float64)
-        self.check(lib.qdp_baryon_contract(self.h, _u64_array(Su), _u64_array(Sd), BARYON_PROTON, parity, t0,
+        self.check(lib.qdp_baryon_contract(self.h, a, b, BARYON_PROTON, parity, t0,
                                            j_decay, out.ctypes.data_as(_dp)))
         return out.view(np.complex128)
 
     def delta(self, S, parity=1, t0=0, j_decay=3):
         """Delta++ two-point function C(t) (summed over mu = 1, 2, 3), shape (Lt,) complex."""
+        a = _propagator(S, "delta S")
         lat = self.field_meta[S[0]][0]
         Lt = self.lattice_dims[lat][3]
         out = np.zeros(Lt * 2, dtype=np.float64)
-        self.check(lib.qdp_baryon_contract(self.h, _u64_array(S), None, BARYON_DELTA_PP, parity, t0, j_decay,
+        self.check(lib.qdp_baryon_contract(self.h, a, None, BARYON_DELTA_PP, parity, t0, j_decay,
                                            out.ctypes.data_as(_dp)))
         return out.view(np.complex128)
 

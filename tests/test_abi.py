@@ -37,3 +37,23 @@ def test_null_arguments_are_rejected_without_a_device():
     assert qdpmi.lib.qdp_init(None, None) == -1
     assert qdpmi.lib.qdp_last_error(None) == b"null context"
     assert qdpmi.lib.qdp_sync(None) == -1
+
+
+def test_binding_refuses_propagators_without_12_columns():
+    """The contraction entry points read exactly 12 column handles; the
+    binding refuses any other count before calling the library (no context
+    or device is needed to reach the check)."""
+    import pytest
+
+    from paper_1111_5596_amd import qdpmi
+
+    ctx = qdpmi.Context.__new__(qdpmi.Context)  # no library context behind it
+    eleven, thirteen, twelve = list(range(1, 12)), list(range(1, 14)), list(range(1, 13))
+    calls = [lambda S: ctx.contract(S, twelve), lambda S: ctx.contract(twelve, S),
+             lambda S: ctx.contract_mom(S, twelve, [(0, 0, 0)]), lambda S: ctx.nucleon(twelve, S),
+             lambda S: ctx.nucleon(S, twelve), lambda S: ctx.delta(S)]
+    for call in calls:
+        for bad in (eleven, thirteen, []):
+            with pytest.raises(ValueError, match="12 column handles"):
+                call(bad)
+    assert len(qdpmi._propagator(twelve, "x")) == 12

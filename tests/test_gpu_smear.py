@@ -235,6 +235,64 @@ def test_batch_equals_single_bitwise(qdp):
         free_all(qdp, [g, g2] + fs + fs2)
 
 
+def _device_equal(q, a, b):
+    """Bitwise equality of two FERMION fields on the device: the FP64 sum of
+    |a - b|^2 over all sites is exactly 0 only if every difference is 0."""
+    d = q.sum_multi([("field", a), ("field", b), ("sub",), ("local_norm2",)], "all", 1, 1)
+    return d[0, 0].real == 0.0
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1, 2, 0, 0), (2, 2, 0, 0, 0, 0), None])
+def test_batch_blocks_walk_across_lattices_bitwise(qdp, shape):
+    """More work items than the persistent grid has blocks: the lattices hold
+    over 10k (lattice, 64-site tile) items, above the most 64-thread blocks
+    256 CUs can hold (32 waves each), so blocks take several items, and their
+    later items lie in other lattices.  Every column of every lattice must
+    equal the one-lattice smearing bitwise; two columns of the small lattices
+    are also checked against the oracle."""
+    sizes = [(16, 16, 16, 32), (6, 6, 6, 4), (16, 16, 16, 32), (12, 12, 12, 24), (16, 16, 16, 32),
+             (8, 8, 8, 16), (16, 16, 16, 32), (16, 16, 16, 32), (4, 4, 4, 8)]
+    items = sum(2 * -(-synth.volume(d) // 2 // 64) for d in sizes)
+    assert items > 256 * 32
+    niter = 5
+    if shape is not None:
+        qdp.set_shape(*shape)
+    try:
+        jobs, single, small = [], [], []
+        for j, dims in enumerate(sizes):
+            lat = qdp.lattice(dims)
+            g = qdp.alloc(lat, "GAUGE", "F32")
+            qdp.fill_random_su3(g, 4101 + j)
+            fs = [qdp.alloc(lat, "FERMION", "F32") for _ in range(12)]
+            fs2 = [qdp.alloc(lat, "FERMION", "F32") for _ in range(12)]
+            scale = (24.0 * synth.volume(dims)) ** -0.5
+            for c, (f, f2) in enumerate(zip(fs, fs2)):
+                qdp.fill_gaussian(f, 4201 + j, c, scale)
+                qdp.fill_gaussian(f2, 4201 + j, c, scale)
+            jobs.append((g, fs, fs))
+            single.append((g, fs2))
+            if synth.volume(dims) <= 4096:
+                small.append((j, dims, fs))
+        qdp.smear_batch(jobs, 0.25, niter)
+        for g, fs2 in single:
+            qdp.smear(g, fs2, 0.25, niter)
+        for j, ((g, fs, _), (_, fs2)) in enumerate(zip(jobs, single)):
+            for c in range(12):
+                assert _device_equal(qdp, fs[c], fs2[c]), (j, c)
+        for j, dims, fs in small:
+            U = synth.su3_links(dims, 4101 + j)
+            src = synth.gaussian_propagator(dims, 4201 + j, columns=[0, 11])
+            ex = oracle.smear(U, src, dims, 0.25, niter)
+            for k, c in enumerate((0, 11)):
+                assert rel(qdp.read(fs[c]), ex[k]) <= 1e-5, (j, c)
+    finally:
+        qdp.set_shape(0)
+        for g, fs, _ in jobs:
+            free_all(qdp, [g] + fs)
+        for _, fs2 in single:
+            free_all(qdp, fs2)
+
+
 def test_zero_iterations_copies(qdp):
     dims = (4, 4, 2, 2)
     psi = synth.gaussian_propagator(dims, 9, ncols=2)
