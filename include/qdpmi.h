@@ -314,6 +314,30 @@ qdp_status qdp_smear_jacobi_batch(qdp_ctx* ctx, const qdp_smear_job* jobs, int32
 qdp_status qdp_hadron_contract(qdp_ctx* ctx, const qdp_field* S1, const qdp_field* S2,
                                uint32_t gamma_mask, int32_t t0, int32_t j_decay, double* out);
 
+/* qdp_hadron_contract without any allocation, for callers that cannot
+ * allocate device or pinned memory during the call (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc).  Same
+ * contraction, same kernels and bitwise the same values as
+ * qdp_hadron_contract, but:
+ * - out_dev is DEVICE memory (8-byte aligned) of 16 * Lt * 2 doubles in the
+ *   layout of qdp_hadron_contract's out, written in order on the context
+ *   stream; the call does not synchronise (read out_dev after qdp_sync or
+ *   after work ordered behind the stream);
+ * - the per-block partial sums go to a fixed 4 MiB device array of the
+ *   library (one per GPU, held until the process ends) instead of a pool
+ *   temporary: 256 * Lt * min(ceil(8192 / Lt), ceil(Lx Ly Lz / 64)) bytes,
+ *   within the 4 MiB for every Lt <= 16384; larger needs give
+ *   QDP_ERR_UNSUPPORTED;
+ * - every column must be resident on the device (a spilled column gives
+ *   QDP_ERR_STATE; the call never refills it).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams or other contexts) race.  Each call writes every
+ * partial sum it reads, so none needs clearing.  Errors: as
+ * qdp_hadron_contract; QDP_ERR_ARG (null or misaligned out_dev),
+ * QDP_ERR_STATE (spilled column), QDP_ERR_UNSUPPORTED (scratch size). */
+qdp_status qdp_hadron_contract_noalloc(qdp_ctx* ctx, const qdp_field* S1, const qdp_field* S2,
+                                       uint32_t gamma_mask, int32_t t0, int32_t j_decay, double* out_dev);
+
 /* Momentum-projected meson correlators (the hadron spectrum's plane-wave
  * projections, HAD of section 5):
  *   C_n(p, t) = sum_{x: x_3 = t} exp(-i p.x) Tr[ g5 S2^dagger g5 Gamma_n S1 Gamma_n ](x)

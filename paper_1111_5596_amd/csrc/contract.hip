@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -635,20 +636,31 @@ void* meson_func(int prec, bool buf, bool mom) {
 }
 }  // namespace
 
-qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
-                                int32_t t0, int32_t j_decay, const int32_t* moms, int32_t nmom, double* out) {
+namespace {
+// Checks the 24 column handles, pins the columns (resident_only: fail
+// instead of filling a column from host memory) and fills the kernel
+// arguments shared by the contraction entry points.
+qdp_status meson_setup(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, int32_t j_decay, bool resident_only,
+                       PinSet& pins, ContractArgs* a, GammaDev* gd, int32_t* prec_out) {
     if (j_decay != 3) return set_error(ctx, QDP_ERR_UNSUPPORTED, "contract: only j_decay = 3 (time)");
-    if (nmom < 0 || (nmom > 0 && !moms)) return set_error(ctx, QDP_ERR_ARG, "contract: bad momentum list");
     uint64_t lat = 0;
     int32_t prec = -1;
     for (int side = 0; side < 2; ++side)
         for (int c = 0; c < 12; ++c) {
-            Field* f = find_field(ctx, side ? S2[c] : S1[c]);
+            const uint64_t id = side ? S2[c] : S1[c];
+            Field* f = find_field(ctx, id);
             if (!f) return set_error(ctx, QDP_ERR_STATE, "contract: unknown column handle");
             if (f->type != QDP_FERMION) return set_error(ctx, QDP_ERR_TYPE, "contract: columns must be FERMION");
             if (lat && f->lattice != lat) return set_error(ctx, QDP_ERR_LATTICE, "contract: columns on different lattices");
             if (prec >= 0 && f->prec != prec)
                 return set_error(ctx, QDP_ERR_UNSUPPORTED, "contract: all 24 columns must share one precision");
+            if (resident_only) {
+                const CacheEntry* e = ctx->cache.find(id);
+                if (!e || !e->on_device)
+                    return set_error(ctx, QDP_ERR_STATE,
+                                     "contract: column %llu is spilled to host memory; this call does not refill it",
+                                     (unsigned long long)id);
+            }
             lat = f->lattice;
             prec = f->prec;
         }
@@ -658,55 +670,82 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
     int64_t nchunks = (8192 + Lt - 1) / Lt;
     nchunks = std::max<int64_t>(1, std::min<int64_t>(nchunks, (Vs + 63) / 64));
 
-    PinSet pins(ctx);
-    ContractArgs a{};
-    a.g = g;
+    *a = ContractArgs{};
+    a->g = g;
     for (int c = 0; c < 12; ++c) {
         char* p;
         QDP_CHECK(pins.add(S1[c], true, &p));
-        a.s1[c] = p;
+        a->s1[c] = p;
         QDP_CHECK(pins.add(S2[c], true, &p));
-        a.s2[c] = p;
+        a->s2[c] = p;
     }
-    a.nchunks = (int32_t)nchunks;
+    a->nchunks = (int32_t)nchunks;
+
+    for (int sg = 0; sg < 4; ++sg)
+        for (int i = 0; i < 4; ++i) {
+            gd->perm[sg][i] = (int8_t)ctx->gamma.group_perm[sg][i];
+            gd->members[sg][i] = (int8_t)ctx->gamma.group_members[sg][i];
+        }
+    for (int n = 0; n < 16; ++n)
+        for (int i = 0; i < 4; ++i) {
+            gd->pcode[n][i] = (int8_t)phase_code(ctx->gamma.p_phase[n][i]);
+            gd->qcode[n][i] = (int8_t)phase_code(ctx->gamma.q_phase[n][i]);
+        }
+    *prec_out = prec;
+    return QDP_OK;
+}
+
+// Bytes of the per-block partial sums of one meson launch carrying nq momenta.
+size_t meson_partial_bytes(const ContractArgs& a, int32_t nq) {
+    return sizeof(double) * 2 * 16 * (size_t)nq * a.g.L[3] * (size_t)a.nchunks;
+}
+
+// One meson launch (a.partial set, a.mom the launch's momenta) and its
+// fixed-order finish into d_out: nq * 16 * Lt complex values.
+qdp_status meson_launch(Ctx* ctx, ContractArgs& a, const GammaDev& gd, int32_t prec, bool mom, uint32_t mask,
+                        int32_t t0, double* d_out) {
+    const int32_t Lt = a.g.L[3];
+    const int32_t nq = mom ? kMomPerLaunch : 1;
+    GammaDev gcopy = gd;
+    void* args[] = {&a, &gcopy};
+    const bool buf = field_bytes(a.g, QDP_FERMION, prec) < (int64_t(1) << 32);
+    QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)a.nchunks, (unsigned)Lt), dim3(256),
+                                 args, 0, ctx->stream));
+    QDP_CHECK(check_launch(ctx, "meson kernel"));
+    const int nthreads = nq * 16 * Lt;
+    hipLaunchKernelGGL(meson_finish, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
+                       a.nchunks, nq, mask, t0, d_out);
+    return check_launch(ctx, "meson finish kernel");
+}
+}  // namespace
+
+qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
+                                int32_t t0, int32_t j_decay, const int32_t* moms, int32_t nmom, double* out) {
+    if (nmom < 0 || (nmom > 0 && !moms)) return set_error(ctx, QDP_ERR_ARG, "contract: bad momentum list");
+    PinSet pins(ctx);
+    ContractArgs a;
+    GammaDev gd;
+    int32_t prec;
+    QDP_CHECK(meson_setup(ctx, S1, S2, j_decay, false, pins, &a, &gd, &prec));
+    const int32_t Lt = a.g.L[3];
     const bool mom = nmom > 0;
     const int32_t nq = mom ? kMomPerLaunch : 1;  // momenta per launch
     const int32_t nlaunch = mom ? (nmom + kMomPerLaunch - 1) / kMomPerLaunch : 1;
     PoolTemp scratch;
-    const size_t partial_bytes = sizeof(double) * 2 * 16 * (size_t)nq * Lt * nchunks;
+    const size_t partial_bytes = meson_partial_bytes(a, nq);
     const size_t launch_out_bytes = sizeof(double) * 2 * 16 * (size_t)nq * Lt;
     const size_t out_bytes = sizeof(double) * 2 * 16 * (size_t)Lt * (mom ? nmom : 1);
     QDP_CHECK(scratch.alloc(ctx, (int64_t)(partial_bytes + launch_out_bytes * nlaunch + 256)));
     a.partial = reinterpret_cast<double*>(scratch.ptr());
     double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
 
-    GammaDev gd;
-    for (int sg = 0; sg < 4; ++sg)
-        for (int i = 0; i < 4; ++i) {
-            gd.perm[sg][i] = (int8_t)ctx->gamma.group_perm[sg][i];
-            gd.members[sg][i] = (int8_t)ctx->gamma.group_members[sg][i];
-        }
-    for (int n = 0; n < 16; ++n)
-        for (int i = 0; i < 4; ++i) {
-            gd.pcode[n][i] = (int8_t)phase_code(ctx->gamma.p_phase[n][i]);
-            gd.qcode[n][i] = (int8_t)phase_code(ctx->gamma.q_phase[n][i]);
-        }
-
-    void* args[] = {&a, &gd};
-    const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
     for (int32_t L = 0; L < nlaunch; ++L) {
         for (int q = 0; q < kMomPerLaunch; ++q)
             for (int i = 0; i < 3; ++i) {
                 const int32_t k = L * kMomPerLaunch + q;
                 a.mom[q][i] = (mom && k < nmom) ? moms[3 * k + i] : 0;
             }
-        QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256),
-                                     args, 0, ctx->stream));
-        QDP_CHECK(check_launch(ctx, "meson kernel"));
-        const int nthreads = nq * 16 * Lt;
-        hipLaunchKernelGGL(meson_finish, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
-                           (int32_t)nchunks, nq, mask, t0, d_out + (size_t)L * nq * 16 * Lt * 2);
-        QDP_CHECK(check_launch(ctx, "meson finish kernel"));
+        QDP_CHECK(meson_launch(ctx, a, gd, prec, mom, mask, t0, d_out + (size_t)L * nq * 16 * Lt * 2));
     }
     double* host;
     QDP_CHECK(host_result_buffer(ctx, out_bytes, &host));
@@ -714,6 +753,61 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
     QDP_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::memcpy(out, host, out_bytes);
     return QDP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free zero-momentum contraction: the per-block partial sums live
+// in a fixed device array of the library instead of a pool temporary.  The
+// array is one per GPU; its device address is looked up once per device
+// when a context is created there (in host code the array's name is not a
+// device address).  Calls on one GPU share it, so calls that overlap in time
+// on one GPU (two streams or two contexts) race; every call writes all of
+// the partial sums it reads, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+qdp_status noalloc_scratch_init(Ctx* ctx) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return set_error(ctx, QDP_ERR_ARG, "device index %d out of range", ctx->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[ctx->device]) {
+        void* p = nullptr;
+        // the calling thread has ctx->device current (qdp_init set it)
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_error(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                    "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[ctx->device] = p;
+    }
+    ctx->noalloc_scratch = g_scratch_dev[ctx->device];
+    return QDP_OK;
+}
+
+qdp_status hadron_contract_noalloc_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
+                                        int32_t t0, int32_t j_decay, double* out_dev) {
+    if (!out_dev) return set_error(ctx, QDP_ERR_ARG, "contract_noalloc: null output");
+    if (reinterpret_cast<uintptr_t>(out_dev) % alignof(double))
+        return set_error(ctx, QDP_ERR_ARG, "contract_noalloc: output not 8-byte aligned");
+    if (!ctx->noalloc_scratch) return set_error(ctx, QDP_ERR_STATE, "contract_noalloc: scratch array not set up");
+    PinSet pins(ctx);
+    ContractArgs a;
+    GammaDev gd;
+    int32_t prec;
+    QDP_CHECK(meson_setup(ctx, S1, S2, j_decay, true, pins, &a, &gd, &prec));
+    const size_t partial_bytes = meson_partial_bytes(a, 1);
+    if (partial_bytes > kNoAllocScratchBytes)
+        return set_error(ctx, QDP_ERR_UNSUPPORTED,
+                         "contract_noalloc: %zu bytes of partial sums (Lt %d) exceed the %zu-byte scratch array",
+                         partial_bytes, a.g.L[3], kNoAllocScratchBytes);
+    a.partial = static_cast<double*>(ctx->noalloc_scratch);
+    return meson_launch(ctx, a, gd, prec, false, mask, t0, out_dev);
 }
 
 namespace {

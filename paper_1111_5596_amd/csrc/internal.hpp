@@ -75,6 +75,10 @@ struct Ctx {
     double* host_result = nullptr;
     size_t host_result_bytes = 0;
 
+    // device address of this device's copy of the allocation-free
+    // contraction's scratch array (looked up at qdp_init)
+    void* noalloc_scratch = nullptr;
+
     // smearing: launch-shape tuning and graph cache
     std::map<SmearTuneKey, qdp_launch_shape> tuned;
     std::map<std::string, qdp_launch_shape> tuned_batch;  // keyed by precision, every lattice and column count
@@ -173,6 +177,9 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
                             int32_t n_iter);
 qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
                                 int32_t t0, int32_t j_decay, const int32_t* moms, int32_t nmom, double* out);
+qdp_status hadron_contract_noalloc_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, uint32_t mask,
+                                        int32_t t0, int32_t j_decay, double* out_dev);
+qdp_status noalloc_scratch_init(Ctx* ctx);
 qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd, int32_t kind, int32_t parity,
                                 int32_t t0, int32_t j_decay, double* out);
 qdp_status eval_impl(Ctx* ctx, const qdp_expr* expr, uint64_t dest, qdp_subset subset,

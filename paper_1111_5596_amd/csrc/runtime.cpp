@@ -331,6 +331,7 @@ qdp_status qdp_init(const qdp_init_opts* opts, qdp_ctx** out) {
     ctx->cache.reset(opts->pool_bytes, opts->host_spill_bytes, &ctx->mover);
     if (const char* env = std::getenv("QDP_FAULT_ALLOC_AFTER")) ctx->cache.fault_after(std::atoll(env));
     build_gamma_tables(ctx);
+    if (noalloc_scratch_init(ctx) != QDP_OK) return fail(QDP_ERR_HIP);
     *out = ctx;
     return QDP_OK;
 }
@@ -669,6 +670,15 @@ qdp_status qdp_hadron_contract(qdp_ctx* ctx, const qdp_field* S1, const qdp_fiel
     if (!S1 || !S2 || !out) return set_error(ctx, QDP_ERR_ARG, "null argument");
     QDP_API_BEGIN
     return hadron_contract_impl(ctx, S1, S2, gamma_mask, t0, j_decay, nullptr, 0, out);
+    QDP_API_END(ctx)
+}
+
+qdp_status qdp_hadron_contract_noalloc(qdp_ctx* ctx, const qdp_field* S1, const qdp_field* S2,
+                                       uint32_t gamma_mask, int32_t t0, int32_t j_decay, double* out_dev) {
+    if (!ctx) return QDP_ERR_ARG;
+    if (!S1 || !S2 || !out_dev) return set_error(ctx, QDP_ERR_ARG, "null argument");
+    QDP_API_BEGIN
+    return hadron_contract_noalloc_impl(ctx, S1, S2, gamma_mask, t0, j_decay, out_dev);
     QDP_API_END(ctx)
 }
 

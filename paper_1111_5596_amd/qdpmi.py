@@ -112,6 +112,7 @@ SIGNATURES = {
     "qdp_smear_jacobi_to": (_i32, [_vp, _u64, _u64p, _u64p, _i32, _dbl, _i32, _i32, _i32]),
     "qdp_smear_jacobi_batch": (_i32, [_vp, _c.POINTER(qdp_smear_job), _i32, _dbl, _i32]),
     "qdp_hadron_contract": (_i32, [_vp, _u64p, _u64p, _u32, _i32, _i32, _dp]),
+    "qdp_hadron_contract_noalloc": (_i32, [_vp, _u64p, _u64p, _u32, _i32, _i32, _vp]),
     "qdp_hadron_contract_mom": (_i32, [_vp, _u64p, _u64p, _u32, _c.POINTER(_c.c_int32), _i32, _i32, _i32,
                                        _dp]),
     "qdp_baryon_contract": (_i32, [_vp, _u64p, _u64p, _i32, _i32, _i32, _i32, _dp]),
@@ -349,6 +350,13 @@ class Context:
         self.check(lib.qdp_hadron_contract(self.h, a, b, mask, t0, j_decay,
                                            out.ctypes.data_as(_dp)))
         return out.view(np.complex128).reshape(16, Lt)
+
+    def contract_noalloc(self, S1, S2, out_ptr, mask=0xFFFF, t0=0, j_decay=3):
+        """qdp_hadron_contract_noalloc: writes 16 * Lt complex FP64 values
+        (the layout of `contract`) to the device address out_ptr, ordered on
+        the context stream, without synchronising."""
+        a, b = _propagator(S1, "contract_noalloc S1"), _propagator(S2, "contract_noalloc S2")
+        self.check(lib.qdp_hadron_contract_noalloc(self.h, a, b, mask, t0, j_decay, _vp(out_ptr)))
 
     def contract_mom(self, S1, S2, moms, mask=0xFFFF, t0=0, j_decay=3):
         """C_n(p, t), shape (nmom, 16, Lt), for integer momenta `moms`."""
