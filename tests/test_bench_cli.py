@@ -30,6 +30,7 @@ def test_byte_model_matches_record_sizes():
     assert bench.pass_bytes(V, "F16S", True) / (12 * V / 2) == pytest.approx(176.0)
     assert bench.pass_bytes(V, "F32", False) / (12 * V) == pytest.approx(210.0)
     assert bench.MODEL_BYTES_PER_SITE_UPDATE[("F16S", True)] == 124
+    assert bench.MODEL_BYTES_PER_SITE_UPDATE[("F16S", False)] == 114
 
 
 def test_traffic_record_parses_and_is_keyed_to_the_kernel():
@@ -42,11 +43,15 @@ def test_traffic_record_parses_and_is_keyed_to_the_kernel():
                 rec[k.strip()] = v.strip()
     assert float(rec["traffic_bytes_per_launch"]) > float(rec["write_size_bytes_per_launch"]) > 0
     assert len(rec["kernel_source_sha256"]) == 64
+    mode = rec.get("launch_mode", "even_odd")
+    assert mode in ("full", "even_odd")
     # the record is reported only while it matches the kernel sources
-    assert (bench.measured_traffic() is None) == (rec["kernel_source_sha256"] != bench.kernel_source_digest())
-    # and only for the launch shape it was measured with
+    stale = rec["kernel_source_sha256"] != bench.kernel_source_digest()
+    assert (bench.measured_traffic(mode=mode) is None) == stale
+    # and only for the launch shape and mode it was measured with
     shape = tuple(int(x) for x in rec["launch_shape_tuple"].split(","))
     assert len(shape) == 6
-    assert (bench.measured_traffic(shape) is None) == (bench.measured_traffic() is None)
+    assert (bench.measured_traffic(shape, mode) is None) == stale
     other = (shape[0] % 4 + 1,) + shape[1:]
-    assert bench.measured_traffic(other) is None
+    assert bench.measured_traffic(other, mode) is None
+    assert bench.measured_traffic(shape, "even_odd" if mode == "full" else "full") is None
