@@ -45,7 +45,8 @@
  * - Precisions: QDP_F64, QDP_F32, and QDP_F16S: IEEE half storage of every
  *   component with one FP32 scale per site record (one fermion column at a
  *   site, or one colour matrix of a site), scale = 2^e with e the binary
- *   exponent of the record's largest |component| (1 for an all-zero record),
+ *   exponent of the record's largest |component| (2^-126, the smallest normal
+ *   FP32 power of two, for an all-zero record),
  *   stored value = round-to-nearest-even(v / scale).  Arithmetic on F16S
  *   fields is FP32.
  */
@@ -489,7 +490,16 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
  * block 64-site tiles one (x, y) plane apart (the tiles of z-neighbouring
  * sites, so that the neighbour records they share are read by one CU;
  * single-lattice launches with site_waves > 1, ignored otherwise) instead of
- * consecutive tiles.  Every shape computes bitwise-identical results.
+ * consecutive tiles (zstack = 2: on whole-lattice updates with one column
+ * group and an even site_waves, half of a block's waves take even tiles and
+ * half the odd tiles with the same indices, z-stacked; elsewhere as 1),
+ * lds = S (1 or 2; 0 = off) runs whole-lattice F16S
+ * updates (QDP_SMEAR_FULL) with the kernel that stages each block's x/y
+ * neighbour window in LDS, blocks of 2 S wavefronts updating 64 S
+ * checkerboard indices of both parities (site_waves, col_groups,
+ * waves_per_simd and zstack do not apply to it; other launches, or
+ * lattices whose window does not fit in 64 KB of LDS, ignore lds).
+ * Every shape computes bitwise-identical results.
  * qdp_smear_set_shape forces a shape (site_waves = 0 returns to
  * autotuning); qdp_smear_get_shape reports the shape the last smearing call
  * used. */
@@ -500,6 +510,7 @@ typedef struct {
     int32_t waves_per_simd;
     int32_t flat;
     int32_t zstack;
+    int32_t lds;
 } qdp_launch_shape;
 qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape);
 qdp_status qdp_smear_get_shape(qdp_ctx* ctx, qdp_launch_shape* out);

@@ -1,10 +1,11 @@
 """Build libqdpmi.so (HIP, gfx950) in-tree.
 
-    python -m paper_1111_5596_amd.build
+    python -m paper_1111_5596_amd.build [--incremental] [-v]
 
 Every translation unit under csrc/ is compiled with hipcc for gfx950 in
 parallel and linked into paper_1111_5596_amd/libqdpmi.so.  Packed FP32
-instructions are disabled for all device code.
+instructions are disabled for all device code.  --incremental recompiles
+only the units older than a source or header under csrc/ or include/.
 """
 
 from __future__ import annotations
@@ -31,9 +32,18 @@ COMMON = [
 SOURCES = ["runtime.cpp", "smear.hip", "contract.hip", "eval.hip", "synth.hip"]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _newest_header() -> float:
+    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    paths += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def _compile(src: str, verbose: bool, incremental: bool = False) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(path),
+                                                                            _newest_header()):
+        return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     cmd = [HIPCC, *lang, *COMMON, "-c", path, "-o", obj]
     if verbose:
@@ -47,11 +57,11 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, min(os.cpu_count() or 1, 16)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5", *objs, "-o", tmp]
     if verbose:
@@ -64,4 +74,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

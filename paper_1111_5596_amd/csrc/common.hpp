@@ -56,6 +56,11 @@ QDP_HD inline TypeShape type_shape(int32_t type) {
 QDP_HD inline bool valid_type(int32_t t) { return t >= QDP_REAL && t <= QDP_GAUGE; }
 QDP_HD inline bool valid_prec(int32_t p) { return p >= QDP_F64 && p <= QDP_F16S; }
 
+// F16S scale of an all-zero record: the smallest normal FP32 power of two
+// (any scale decodes zeros; this one never outweighs a non-zero record when
+// the smearing brings the records of a site's neighbours to a common scale).
+constexpr float kF16sZeroScale = 0x1p-126f;
+
 // Bytes per complex component in a plane.
 QDP_HD inline int64_t prec_complex_bytes(int32_t prec) {
     return prec == QDP_F64 ? 16 : (prec == QDP_F32 ? 8 : 4);

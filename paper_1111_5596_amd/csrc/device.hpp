@@ -48,10 +48,42 @@ __device__ __forceinline__ void cmac_conj(T2& acc, const T2& u, const T2& v) {
 }
 
 // Scale factor of an F16S record: 2^e with e the binary exponent of the
-// largest magnitude m (m = f 2^e, 0.5 <= f < 1); 1 for an all-zero record.
-// Returns e (0 for zero).
+// largest magnitude m (m = f 2^e, 0.5 <= f < 1); kF16sZeroScale for an
+// all-zero record.  Returns e (0 for zero; the caller stores
+// f16s_scale(m, e)).
 __device__ __forceinline__ int f16s_exponent(float m) {
     return m > 0.f ? __builtin_amdgcn_frexp_expf(m) : 0;
+}
+__device__ __forceinline__ float f16s_scale(float m, int e) {
+    return m > 0.f ? __builtin_ldexpf(1.0f, e) : kF16sZeroScale;
+}
+
+// a * b + (float)h.x and a * b + (float)h.y in one rounding (v_fma_mix_f32:
+// the half operand is widened exactly inside the instruction).
+__device__ __forceinline__ float fma_mix_lo(float a, float b, half2_t h) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(a), "v"(b), "v"(h));
+    return r;
+}
+__device__ __forceinline__ float fma_mix_hi(float a, float b, half2_t h) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(a), "v"(b), "v"(h));
+    return r;
+}
+// max(|a|, |b|, c) in one instruction (c >= 0)
+__device__ __forceinline__ float max3_abs(float a, float b, float c) {
+    float r;
+    asm("v_max3_f32 %0, |%1|, |%2|, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+// (half(x * s), half(y * s)) with one rounding each (v_fma_mixlo_f16 /
+// v_fma_mixhi_f16 with a zero addend); for s a power of two the products are
+// exact, so this is the round-to-nearest-even FP16 of x * s and y * s.
+__device__ __forceinline__ half2_t mul_to_half2(float x, float y, float s) {
+    half2_t r;
+    asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(r) : "v"(x), "v"(s));
+    asm("v_fma_mixhi_f16 %0, %1, %2, 0" : "+v"(r) : "v"(y), "v"(s));
+    return r;
 }
 
 __device__ __forceinline__ half2_t f16s_encode(float re, float im, int e) {

@@ -263,7 +263,7 @@ __device__ __forceinline__ void store_values(const OutDesc& out, const Geometry&
             *reinterpret_cast<half2_t*>(out.base + comp_offset(out.nrec, out.ncomp, out.prec, 0, k, s)) =
                 f16s_encode((float)v[k].x, out.real_only ? 0.f : (float)v[k].y, e);
         *reinterpret_cast<float*>(out.base + scale_offset(out.nrec, out.ncomp, 0, s)) =
-            m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
+            f16s_scale(m, e);
     }
 }
 

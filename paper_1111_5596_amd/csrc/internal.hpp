@@ -82,8 +82,8 @@ struct Ctx {
     // smearing: launch-shape tuning and graph cache
     std::map<SmearTuneKey, qdp_launch_shape> tuned;
     std::map<std::string, qdp_launch_shape> tuned_batch;  // keyed by precision, every lattice and column count
-    qdp_launch_shape forced{0, 0, 0, 0, 0, 0};
-    qdp_launch_shape last_shape{0, 0, 0, 0, 0, 0};
+    qdp_launch_shape forced{0, 0, 0, 0, 0, 0, 0};
+    qdp_launch_shape last_shape{0, 0, 0, 0, 0, 0, 0};
     std::map<std::string, GraphEntry> graphs;
     uint64_t graph_tick = 0;
 

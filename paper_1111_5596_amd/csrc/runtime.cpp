@@ -194,7 +194,7 @@ void encode_f16s(const float* v, int n, _Float16* q, float* scale) {
     for (int i = 0; i < 2 * n; ++i) m = std::max(m, std::fabs(v[i]));
     int e = 0;
     if (m > 0.f) std::frexp(m, &e);
-    *scale = m > 0.f ? std::ldexp(1.0f, e) : 1.0f;
+    *scale = m > 0.f ? std::ldexp(1.0f, e) : kF16sZeroScale;
     for (int i = 0; i < 2 * n; ++i) q[i] = (_Float16)std::ldexp(v[i], -e);
 }
 
@@ -612,8 +612,9 @@ qdp_status qdp_smear_set_shape(qdp_ctx* ctx, const qdp_launch_shape* shape) {
         const int sw = shape->site_waves, cg = shape->col_groups;
         if (sw < 1 || cg < 1 || cg > 12 || sw * cg > 4 || shape->xcd < 0 || shape->xcd > 2 ||
             !(shape->waves_per_simd == 0 || shape->waves_per_simd == 2 || shape->waves_per_simd == 3) ||
-            shape->flat < 0 || shape->flat > 1 || shape->zstack < 0 || shape->zstack > 1)
-            return set_error(ctx, QDP_ERR_ARG, "launch shape out of range (site_waves * col_groups <= 4)");
+            shape->flat < 0 || shape->flat > 1 || shape->zstack < 0 || shape->zstack > 2 || shape->lds < 0 ||
+            shape->lds > 2)
+            return set_error(ctx, QDP_ERR_ARG, "launch shape out of range (site_waves * col_groups <= 4, lds <= 2)");
     }
     ctx->forced = *shape;
     return QDP_OK;

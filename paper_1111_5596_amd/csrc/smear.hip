@@ -146,8 +146,148 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
 // Per-site update, F16S storage (FP32 arithmetic)
 // ---------------------------------------------------------------------------
 
+// Always the VOP3P v_dot2_f32_f16 (inline asm): left to the compiler, the
+// accumulating form is emitted as the VOP2 v_dot2c_f32_f16 or as the VOP3P
+// instruction depending on register allocation, and the two need not agree
+// on subnormal half inputs, which would make launch shapes differ in bits.
 __device__ __forceinline__ float dot2(half2_t a, half2_t b, float c) {
-    return __builtin_amdgcn_fdot2(a, b, c, false);
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// The F16S update of one site and column, shared by every kernel variant so
+// that all of them produce the same bits.  The six hop terms are taken in the
+// fixed order z forward, z backward, y forward, y backward, x forward, x
+// backward (hop h: direction kHopDir[h], backward when h is odd).
+constexpr int kHopDir[6] = {2, 2, 1, 1, 0, 0};
+
+// The links of one site in the two half2 forms the products need, per hop:
+// forward link u = U_i(x):        re(u v) = (u.x, -u.y).v  im(u v) = (u.y, u.x).v
+// backward link w = U_i(x - i)^T: re(w* v) = (w.x, w.y).v   im(w* v) = (-w.y, w.x).v
+// element [3 a + b] of a hop multiplies colour b of the neighbour into colour
+// a of the result (the backward link stored transposed), with the record's
+// FP32 scale.
+struct F16sLinks {
+    half2_t re[6][9], im[6][9];
+    float s[6];
+};
+
+template <bool BUF>
+__device__ __forceinline__ void load_links_f16s(const char* gauge, int32_t s, const SpatialNeighbours& nb,
+                                                F16sLinks& L) {
+    const int64_t tbu = tile_bytes(4, 9, QDP_F16S);
+    const ChunkRef<BUF> U(gauge);
+    const FieldRef<float, BUF> Us(gauge);
+    const int64_t us = tile_site_offset(tbu, 16, s), us4 = site_off<float>(s, tbu);
+    half2_t u[27], w[3][9];
+    load_elems<0, 27>(U, us, u);
+    load_elems<0, 9>(U, tile_site_offset(tbu, 16, nb.bwd[0]), w[0]);
+    load_elems<9, 9>(U, tile_site_offset(tbu, 16, nb.bwd[1]), w[1]);
+    load_elems<18, 9>(U, tile_site_offset(tbu, 16, nb.bwd[2]), w[2]);
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+        const int i = kHopDir[h];
+        if (h & 1) {
+            L.s[h] = Us.load(36 + i, site_off<float>(nb.bwd[i], tbu));
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const half2_t ww = w[i][3 * b + a];
+                    L.re[h][3 * a + b] = ww;
+                    L.im[h][3 * a + b] = half2_t{(_Float16)(-ww.y), ww.x};
+                }
+        } else {
+            L.s[h] = Us.load(36 + i, us4);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const half2_t uu = u[9 * i + k];
+                L.re[h][k] = half2_t{uu.x, (_Float16)(-uu.y)};
+                L.im[h][k] = half2_t{uu.y, uu.x};
+            }
+        }
+    }
+}
+
+// Common scale of the six hop terms.  Hop h multiplies a link record (scale
+// a_h) and a neighbour record (scale b_h), both powers of two; with M the
+// largest p_h = a_h b_h the neighbour's halves are multiplied by p_h / M <= 1
+// (exact in FP16 down to its subnormal range: only terms below 2^-24 of the
+// largest lose bits, as they would in an FP32 sum), so that every product of
+// halves goes, exactly formed, into one FP32 sum per component.
+struct F16sHopScale {
+    float M;
+    half2_t f[6];
+};
+__device__ __forceinline__ F16sHopScale hop_scale_f16s(const F16sLinks& L, const float nsc[6]) {
+    F16sHopScale H;
+    float p[6];
+#pragma unroll
+    for (int h = 0; h < 6; ++h) p[h] = L.s[h] * nsc[h];
+    H.M = fmaxf(fmaxf(fmaxf(p[0], p[1]), fmaxf(p[2], p[3])), fmaxf(p[4], p[5]));
+    const int eM = __builtin_amdgcn_frexp_expf(H.M);  // M = 2^(eM - 1)
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+        const _Float16 f = (_Float16)__builtin_ldexpf(p[h], 1 - eM);
+        H.f[h] = half2_t{f, f};
+    }
+    return H;
+}
+
+// acc (+)= hop h of (1/M) [U psi]: the neighbour record v (as stored) brought
+// to the common scale, then three products per result component.
+template <int H>
+__device__ __forceinline__ void hop_accumulate_f16s(float2 acc[12], const F16sLinks& L, const F16sHopScale& S,
+                                                    const half2_t v_in[12]) {
+    half2_t v[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = v_in[k] * S.f[H];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = acc[3 * sp + a].x, im = acc[3 * sp + a].y;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (H == 0 && b == 0) {
+                    re = dot2_zero(L.re[H][3 * a], v[3 * sp]);
+                    im = dot2_zero(L.im[H][3 * a], v[3 * sp]);
+                } else {
+                    re = dot2(L.re[H][3 * a + b], v[3 * sp + b], re);
+                    im = dot2(L.im[H][3 * a + b], v[3 * sp + b], im);
+                }
+            }
+            acc[3 * sp + a] = make_float2(re, im);
+        }
+}
+
+// psi + kappa M acc in units of R = max(own scale, M) (a power of two):
+// t = acc (kappa M / R) + own (own scale / R), the own halves brought to R in
+// FP16 like the neighbours', one rounding per component; then requantise:
+// the new record's scale is R 2^e with e the binary exponent of max |t|.
+__device__ __forceinline__ float finish_f16s(const float2 acc[12], const half2_t own[12], float so, float M,
+                                             float kappa, half2_t q[12]) {
+    const float R = fmaxf(so, M);
+    const int eR = __builtin_amdgcn_frexp_expf(R);  // R = 2^(eR - 1)
+    const _Float16 fo = (_Float16)__builtin_ldexpf(so, 1 - eR);
+    const half2_t fo2 = {fo, fo};
+    const float kp = kappa * __builtin_ldexpf(M, 1 - eR);
+    float2 t[12];
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const half2_t o = own[k] * fo2;
+        t[k].x = fma_mix_lo(acc[k].x, kp, o);
+        t[k].y = fma_mix_hi(acc[k].y, kp, o);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = max3_abs(t[k].x, t[k].y, m);
+    const int et = f16s_exponent(m);
+    const float inv = __builtin_ldexpf(1.0f, -et);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q[k] = mul_to_half2(t[k].x, t[k].y, inv);
+    return m > 0.f ? __builtin_ldexpf(1.0f, eR - 1 + et) : kF16sZeroScale;
 }
 
 template <bool BUF>
@@ -157,46 +297,17 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
     // data, one per record (row 36 + i of the gauge tile, row 12 of a column
     // tile, counted in 4-byte rows)
     const SpatialNeighbours nb = spatial_neighbours(job.g, s);
-    const int64_t tbu = tile_bytes(4, 9, QDP_F16S), tbc = tile_bytes(1, 12, QDP_F16S);
-    const ChunkRef<BUF> U(job.gauge);
-    const FieldRef<float, BUF> Us(job.gauge);
-    const int64_t us = tile_site_offset(tbu, 16, s), us4 = site_off<float>(s, tbu);
+    const int64_t tbc = tile_bytes(1, 12, QDP_F16S);
     const int64_t cs = tile_site_offset(tbc, 16, s), cs4 = site_off<float>(s, tbc);
-    int64_t ub_off[3], ub4[3], cf[3], cf4[3], cb[3], cb4[3];
+    int64_t n16[6], n4[6];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        ub_off[i] = tile_site_offset(tbu, 16, nb.bwd[i]);
-        ub4[i] = site_off<float>(nb.bwd[i], tbu);
-        cf[i] = tile_site_offset(tbc, 16, nb.fwd[i]);
-        cf4[i] = site_off<float>(nb.fwd[i], tbc);
-        cb[i] = tile_site_offset(tbc, 16, nb.bwd[i]);
-        cb4[i] = site_off<float>(nb.bwd[i], tbc);
+    for (int h = 0; h < 6; ++h) {
+        const int32_t j = (h & 1) ? nb.bwd[kHopDir[h]] : nb.fwd[kHopDir[h]];
+        n16[h] = tile_site_offset(tbc, 16, j);
+        n4[h] = site_off<float>(j, tbc);
     }
-
-    // forward link u: re(u v) = (u.x, -u.y).v   im(u v) = (u.y, u.x).v
-    // backward link w: re(w* v) = (w.x, w.y).v  im(w* v) = (-w.y, w.x).v
-    half2_t fre[3][9], fim[3][9], bre[3][9], bim[3][9];
-    float sf[3], sb[3];
-    {
-        half2_t u[27], w[3][9];
-        load_elems<0, 27>(U, us, u);
-        load_elems<0, 9>(U, ub_off[0], w[0]);
-        load_elems<9, 9>(U, ub_off[1], w[1]);
-        load_elems<18, 9>(U, ub_off[2], w[2]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            sf[i] = Us.load(36 + i, us4);
-            sb[i] = Us.load(36 + i, ub4[i]);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const half2_t uu = u[9 * i + k], ww = w[i][k];
-                fre[i][k] = half2_t{uu.x, (_Float16)(-uu.y)};
-                fim[i][k] = half2_t{uu.y, uu.x};
-                bre[i][k] = ww;
-                bim[i][k] = half2_t{(_Float16)(-ww.y), ww.x};
-            }
-        }
-    }
+    F16sLinks L;
+    load_links_f16s<BUF>(job.gauge, s, nb, L);
 
     for (int c = c0; c < c1; ++c) {
         const ChunkRef<BUF> src(job.src[c]);
@@ -207,74 +318,26 @@ __device__ __forceinline__ void site_update_f16s(const SmearJob& job, int32_t s,
         half2_t v[6][12], own[12];
         float vsc[6], so;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            load_elems<0, 12>(src, cf[i], v[2 * i]);
-            load_elems<0, 12>(src, cb[i], v[2 * i + 1]);
-            vsc[2 * i] = ssc.load(12, cf4[i]);
-            vsc[2 * i + 1] = ssc.load(12, cb4[i]);
+        for (int h = 0; h < 6; ++h) {
+            load_elems<0, 12>(src, n16[h], v[h]);
+            vsc[h] = ssc.load(12, n4[h]);
         }
         load_elems<0, 12, true>(src, cs, own);  // read once: non-temporal
         so = ssc.load(12, cs4);
         __builtin_amdgcn_sched_barrier(0);
 
+        const F16sHopScale S = hop_scale_f16s(L, vsc);
         float2 acc[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            {
-                const half2_t* vv = v[2 * i];
-                const float sc = sf[i] * vsc[2 * i];
-#pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        float tre = dot2_zero(fre[i][3 * a], vv[3 * sp]);
-                        float tim = dot2_zero(fim[i][3 * a], vv[3 * sp]);
-#pragma unroll
-                        for (int b = 1; b < 3; ++b) {
-                            tre = dot2(fre[i][3 * a + b], vv[3 * sp + b], tre);
-                            tim = dot2(fim[i][3 * a + b], vv[3 * sp + b], tim);
-                        }
-                        acc[3 * sp + a].x = fmadd(sc, tre, acc[3 * sp + a].x);
-                        acc[3 * sp + a].y = fmadd(sc, tim, acc[3 * sp + a].y);
-                    }
-            }
-            {
-                const half2_t* vv = v[2 * i + 1];
-                const float sc = sb[i] * vsc[2 * i + 1];
-#pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        float tre = dot2_zero(bre[i][a], vv[3 * sp]);
-                        float tim = dot2_zero(bim[i][a], vv[3 * sp]);
-#pragma unroll
-                        for (int b = 1; b < 3; ++b) {
-                            tre = dot2(bre[i][3 * b + a], vv[3 * sp + b], tre);
-                            tim = dot2(bim[i][3 * b + a], vv[3 * sp + b], tim);
-                        }
-                        acc[3 * sp + a].x = fmadd(sc, tre, acc[3 * sp + a].x);
-                        acc[3 * sp + a].y = fmadd(sc, tim, acc[3 * sp + a].y);
-                    }
-            }
-        }
-        // psi + kappa * acc, then requantise the record
-        float2 out[12];
-        float m = 0.f;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const float2 o = f16s_decode(own[k], so);
-            out[k].x = fmadd(kappa, acc[k].x, o.x);
-            out[k].y = fmadd(kappa, acc[k].y, o.y);
-            m = fmaxf(m, fmaxf(fabsf(out[k].x), fabsf(out[k].y)));
-        }
-        const int e = f16s_exponent(m);
+        hop_accumulate_f16s<0>(acc, L, S, v[0]);
+        hop_accumulate_f16s<1>(acc, L, S, v[1]);
+        hop_accumulate_f16s<2>(acc, L, S, v[2]);
+        hop_accumulate_f16s<3>(acc, L, S, v[3]);
+        hop_accumulate_f16s<4>(acc, L, S, v[4]);
+        hop_accumulate_f16s<5>(acc, L, S, v[5]);
         half2_t q[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) q[k] = f16s_encode(out[k].x, out[k].y, e);
+        const float scale = finish_f16s(acc, own, so, S.M, kappa, q);
         store_elems<12, true>(ChunkRef<BUF>(job.dst[c]), cs, q);
-        FieldRef<float, BUF>(job.dst[c]).store_stream(m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f, 12, cs4);
+        FieldRef<float, BUF>(job.dst[c]).store_stream(scale, 12, cs4);
     }
 }
 
@@ -295,13 +358,12 @@ __device__ __forceinline__ void site_update(const SmearJob& job, int32_t s, int 
 // zstride > 0, tiles zstride apart: blocks p * zstride + r, r < zstride, cover
 // the group of site_waves * zstride tiles starting at tile p * site_waves *
 // zstride, wave w taking tile p * site_waves * zstride + w * zstride + r.
+// `wave` is the wavefront's index among the block's waves of this range.
 template <int PREC, bool BUF>
 __device__ __forceinline__ void tile_update(const SmearJob& job, int64_t tile, int64_t site_begin,
                                            int64_t site_count, int site_waves, int col_groups, int zstride,
-                                           double kappa) {
-    // the wave index is uniform across the wavefront: keep it (and the
-    // column range it selects) in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+                                           double kappa, int wave) {
+    const int lane = threadIdx.x & 63;
     const int group = wave % col_groups, sw = wave / col_groups;
     int64_t t64;
     if (zstride > 0) {
@@ -336,15 +398,221 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
         b = (x + 8 * (j / ln.xcd_group)) * ln.xcd_group + j % ln.xcd_group;
     }
     if (b >= ln.nlogical) return;
-    if (ln.interleave) {
+    // the wave index is uniform across the wavefront: keep it (and the
+    // column range it selects) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (ln.interleave == 2) {
+        // one block, both parities: even waves take the even tiles, odd
+        // waves the odd tiles with the same indices (each other's x, y and,
+        // z-stacked, z neighbours, so they meet in the CU's vector cache)
+        tile_update<PREC, BUF>(job, b, (wave & 1) * job.g.Vh, job.g.Vh, ln.site_waves / 2, 1, ln.zstride,
+                               ln.kappa, wave >> 1);
+    } else if (ln.interleave) {
         // the even tile and the odd tile with the same index are each other's
         // neighbours: updating them together lets the L2 serve both
         const int64_t parity = b & 1;
         tile_update<PREC, BUF>(job, b >> 1, parity * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups,
-                               ln.zstride, ln.kappa);
+                               ln.zstride, ln.kappa, wave);
     } else {
         tile_update<PREC, BUF>(job, b, ln.site_begin, ln.site_count, ln.site_waves, ln.col_groups, ln.zstride,
-                               ln.kappa);
+                               ln.kappa, wave);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Whole-lattice F16S update with the x/y neighbour window staged in LDS
+// ---------------------------------------------------------------------------
+// A block of 2 S wavefronts updates the checkerboard index range
+// [i0, i0 + 64 S) of both parities (waves 0 .. S-1 the even sites, S .. 2S-1
+// the odd ones).  The x and y neighbours of those sites and the sites
+// themselves lie in the index window [i0 - Lx/2, i0 + 64 S + Lx/2) of the two
+// parities, except where a y hop wraps around the lattice.  Per column the
+// block copies that window of both parities into LDS once, with buffer loads
+// that write LDS directly (no registers), and every thread reads its own
+// record and its x and y neighbours from there instead of fetching each
+// record from the vector cache seven times.  The copy of column c + 1 runs
+// while column c is computed (two LDS buffers, one barrier per column).  The
+// z neighbours come from memory into registers, requested as soon as the
+// current column's z terms are done.  Same per-site arithmetic and hop order
+// as every other variant, so the same bits.
+//
+// LDS buffer layout: rows of Wp = 64 (S + 1) slots, window site w of parity
+// p in slot w (the slots past the window hold copies of its last site and
+// are never read): chunk row r at ((p * 3 + r) * Wp + w) * 16, then the scale
+// rows at 96 Wp + (p * Wp + w) * 4.  The window, 64 S + Lx sites, fits a
+// row for Lx/2 <= 32.  The two buffers are separate arrays and the column
+// loop is unrolled by two, so that every LDS access names its buffer
+// statically: the compiler then knows that reading one buffer does not
+// depend on the copy in flight into the other and does not wait for it.
+constexpr int32_t kLdsMaxHalfX = 32;
+__host__ __device__ constexpr int32_t lds_row_slots(int S) { return 64 * (S + 1); }
+__host__ __device__ constexpr int64_t lds_buffer_bytes(int S) { return (int64_t)lds_row_slots(S) * 104; }
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt vmcnt(0): every load of this wave has landed, including the
+// copies into LDS (whose completion the compiler does not order with the
+// barrier that publishes them to the other waves) and the registers of the
+// next column's z records (so the next column starts with nothing in flight
+// and its first LDS reads need no wait on the copy issued before them).
+__device__ __forceinline__ void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <int S>
+__global__ __launch_bounds__(128 * S) __attribute__((amdgpu_waves_per_eu(2))) void smear_lds_kernel(
+    SmearJob job, SmearLaunch ln) {
+    constexpr int32_t Wp = lds_row_slots(S);
+    __shared__ __attribute__((aligned(16))) char ldsA[lds_buffer_bytes(S)];
+    __shared__ __attribute__((aligned(16))) char ldsB[lds_buffer_bytes(S)];
+    const Geometry& g = job.g;
+    int64_t b = blockIdx.x;
+    if (ln.xcd == 1) b = xcd_logical_block(b, gridDim.x);
+    if (b >= ln.nlogical) return;  // whole block: uniform, before any barrier
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int32_t Vh = (int32_t)g.Vh;
+    const int32_t q = wave >= S ? 1 : 0;  // parity of this wave's sites
+    const int32_t i0 = (int32_t)b * 64 * S;
+    const int32_t i = i0 + 64 * (wave - q * S) + lane;
+    const bool active = i < Vh;
+    const int32_t s = q * Vh + (active ? i : Vh - 1);  // a valid site for the inactive lanes' addresses
+    const int32_t wbeg = max(0, i0 - g.Lxh);
+    const int32_t wlen = min(Vh, i0 + 64 * S + g.Lxh) - wbeg;
+    const int64_t tbc = tile_bytes(1, 12, QDP_F16S);
+
+    const SpatialNeighbours nb = spatial_neighbours(g, s);
+    const int32_t ob = (1 - q) * Vh;
+    // hops 2..5 (y and x) from the window: slot, or -1 when outside it
+    int32_t slot[6];
+#pragma unroll
+    for (int h = 2; h < 6; ++h) {
+        const int32_t j = ((h & 1) ? nb.bwd[kHopDir[h]] : nb.fwd[kHopDir[h]]) - ob - wbeg;
+        slot[h] = (j >= 0 && j < wlen) ? j : -1;
+    }
+    const int32_t own_slot = (s - q * Vh) - wbeg;
+    int64_t n16[6], n4[6];
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+        const int32_t j = (h & 1) ? nb.bwd[kHopDir[h]] : nb.fwd[kHopDir[h]];
+        n16[h] = tile_site_offset(tbc, 16, j);
+        n4[h] = site_off<float>(j, tbc);
+    }
+    const int64_t cs = tile_site_offset(tbc, 16, s), cs4 = site_off<float>(s, tbc);
+    F16sLinks L;
+    load_links_f16s<true>(job.gauge, s, nb, L);
+
+    // copy the window of column c into an LDS buffer: the eight (parity p,
+    // row r; r = 3 the scales) rows dealt to the waves in turn, S + 1 full
+    // 64-lane pieces each (no lane divergence: lanes past the window copy
+    // its last site into padding slots)
+    auto stage = [&](int c, char* base) {
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(job.src[c]);
+        for (int j = wave; j < 8; j += 2 * S) {
+            const int p = j >> 2, r = j & 3;
+#pragma unroll
+            for (int k = 0; k <= S; ++k) {
+                const int32_t site = p * Vh + wbeg + min(64 * k + lane, wlen - 1);
+                if (r < 3)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (lds_void_t*)(base + ((p * 3 + r) * Wp + 64 * k) * 16), 16,
+                        (int)(uint32_t)tile_site_offset(tbc, 16, site), r * 1024, 0, 0);
+                else
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (lds_void_t*)(base + 96 * Wp + (p * Wp + 64 * k) * 4), 4,
+                        (int)(uint32_t)site_off<float>(site, tbc), 12 * 256, 0, 0);
+            }
+        }
+    };
+    auto lds_record = [&](const char* base, int p, int32_t sl, half2_t v[12]) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const Chunk<half2_t> ch = __builtin_bit_cast(
+                Chunk<half2_t>, *reinterpret_cast<const u32x4_t*>(base + ((p * 3 + r) * Wp + sl) * 16));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[4 * r + j] = ch.v[j];
+        }
+    };
+    auto lds_scale = [&](const char* base, int p, int32_t sl) {
+        return *reinterpret_cast<const float*>(base + 96 * Wp + (p * Wp + sl) * 4);
+    };
+
+    // A y hop that wraps around the lattice leaves the window: that record
+    // (at most one per site for Ly >= 3, none for Ly = 2, x hops never) is
+    // fetched from memory with the z neighbours, one column ahead, so that
+    // no wait on memory falls between the start of a column and its barrier.
+    const int32_t xh = slot[2] < 0 ? 2 : (slot[3] < 0 ? 3 : -1);
+    const bool wave_has_x = __builtin_amdgcn_ballot_w64(xh >= 0) != 0;
+    const int64_t x16 = xh == 3 ? n16[3] : n16[2], x4 = xh == 3 ? n4[3] : n4[2];
+
+    const int c1 = job.ncols;
+    half2_t zv[2][12], xv[12];
+    float zsc[2], xsc = 0.f;
+    auto load_z = [&](int c) {
+        const ChunkRef<true> src(job.src[c]);
+        const FieldRef<float, true> ssc(job.src[c]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            load_elems<0, 12>(src, n16[h], zv[h]);
+            zsc[h] = ssc.load(12, n4[h]);
+        }
+        if (wave_has_x && xh >= 0) {
+            load_elems<0, 12>(src, x16, xv);
+            xsc = ssc.load(12, x4);
+        }
+    };
+    // column c from buffer rd while column c + 1 is copied into buffer wr
+    auto column = [&](int c, const char* rd, char* wr) {
+        if (c + 1 < c1) stage(c + 1, wr);
+        float nsc[6];
+        nsc[0] = zsc[0];
+        nsc[1] = zsc[1];
+#pragma unroll
+        for (int h = 2; h < 6; ++h) nsc[h] = lds_scale(rd, 1 - q, max(slot[h], 0));
+        if (wave_has_x) {
+            nsc[2] = xh == 2 ? xsc : nsc[2];
+            nsc[3] = xh == 3 ? xsc : nsc[3];
+        }
+        const float so = lds_scale(rd, q, own_slot);
+        const F16sHopScale H = hop_scale_f16s(L, nsc);
+        float2 acc[12];
+        hop_accumulate_f16s<0>(acc, L, H, zv[0]);
+        hop_accumulate_f16s<1>(acc, L, H, zv[1]);
+        half2_t v[12];
+        lds_record(rd, 1 - q, max(slot[2], 0), v);
+        if (wave_has_x) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) v[k] = xh == 2 ? xv[k] : v[k];
+        }
+        hop_accumulate_f16s<2>(acc, L, H, v);
+        lds_record(rd, 1 - q, max(slot[3], 0), v);
+        if (wave_has_x) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) v[k] = xh == 3 ? xv[k] : v[k];
+        }
+        hop_accumulate_f16s<3>(acc, L, H, v);
+        // the next column's z (and wrapped y) records: the registers are free now
+        if (c + 1 < c1) load_z(c + 1);
+        lds_record(rd, 1 - q, slot[4], v);
+        hop_accumulate_f16s<4>(acc, L, H, v);
+        lds_record(rd, 1 - q, slot[5], v);
+        hop_accumulate_f16s<5>(acc, L, H, v);
+        half2_t own[12], out[12];
+        lds_record(rd, q, own_slot, own);
+        const float scale = finish_f16s(acc, own, so, H.M, (float)ln.kappa, out);
+        if (active) {
+            store_elems<12, true>(ChunkRef<true>(job.dst[c]), cs, out);
+            FieldRef<float, true>(job.dst[c]).store_stream(scale, 12, cs4);
+        }
+        vm_wait_all();
+        __syncthreads();
+    };
+
+    stage(0, ldsA);
+    load_z(0);
+    vm_wait_all();
+    __syncthreads();
+    for (int c = 0; c < c1; c += 2) {
+        column(c, ldsA, ldsB);
+        if (c + 1 < c1) column(c + 1, ldsB, ldsA);
     }
 }
 
@@ -368,7 +636,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
         const SmearJob& job = jobs[j];
         const int64_t u = t - tile_start[j];
         tile_update<PREC, BUF>(job, u >> 1, (u & 1) * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups, 0,
-                               ln.kappa);
+                               ln.kappa, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     }
 }
 
@@ -381,6 +649,7 @@ namespace {
 struct Launch {
     void* func;
     dim3 grid, block;
+    unsigned shmem = 0;      // dynamic LDS bytes
     std::vector<char> args;  // packed argument values
     std::vector<size_t> arg_offsets;
 };
@@ -413,7 +682,7 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
     if (!use_graph || ls.size() < 2) {
         for (auto& L : ls) {
             auto p = arg_pointers(L);
-            QDP_HIP(ctx, hipLaunchKernel(L.func, L.grid, L.block, p.data(), 0, ctx->stream));
+            QDP_HIP(ctx, hipLaunchKernel(L.func, L.grid, L.block, p.data(), L.shmem, ctx->stream));
         }
         return QDP_OK;
     }
@@ -423,6 +692,7 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
         key.append(reinterpret_cast<const char*>(&L.func), sizeof(L.func));
         key.append(reinterpret_cast<const char*>(&L.grid), sizeof(L.grid));
         key.append(reinterpret_cast<const char*>(&L.block), sizeof(L.block));
+        key.append(reinterpret_cast<const char*>(&L.shmem), sizeof(L.shmem));
         key.append(L.args.data(), L.args.size());
     }
     auto it = ctx->graphs.find(key);
@@ -446,7 +716,7 @@ qdp_status run_launches(Ctx* ctx, std::vector<Launch>& ls, bool use_graph) {
             np.func = L.func;
             np.gridDim = L.grid;
             np.blockDim = L.block;
-            np.sharedMemBytes = 0;
+            np.sharedMemBytes = L.shmem;
             np.kernelParams = p.data();
             np.extra = nullptr;
             hipGraphNode_t node;
@@ -500,27 +770,56 @@ void* smear_func(int prec, const qdp_launch_shape& sh, bool batch) {
                    : smear_func_buf<true>(prec, sh.waves_per_simd, batch);
 }
 
+// Whether the LDS-window kernel runs this launch: F16S, the whole lattice,
+// buffer addressing, and a window that fits its LDS rows (Lx <= 64).
+bool lds_eligible(int prec, const SmearJob& job, int64_t begin, int64_t count, const qdp_launch_shape& sh) {
+    if (sh.lds < 1 || sh.lds > 2 || prec != QDP_F16S || sh.flat || begin != 0 || count != job.g.V) return false;
+    return job.g.Lxh <= kLdsMaxHalfX;
+}
+
 // A pass over [begin, begin + count); count == V (the whole lattice) runs
 // the two parities' tiles interleaved.
 Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t count,
                           const qdp_launch_shape& sh, double kappa) {
+    if (lds_eligible(prec, job, begin, count, sh)) {
+        SmearLaunch ln{};
+        ln.site_begin = 0;
+        ln.site_count = job.g.V;
+        ln.interleave = 1;
+        ln.xcd = sh.xcd ? 1 : 0;
+        ln.kappa = kappa;
+        ln.nlogical = (job.g.Vh + 64LL * sh.lds - 1) / (64LL * sh.lds);
+        const int64_t grid = ln.xcd ? (ln.nlogical + 7) / 8 * 8 : ln.nlogical;
+        Launch L;
+        L.func = sh.lds == 1 ? reinterpret_cast<void*>(&smear_lds_kernel<1>)
+                             : reinterpret_cast<void*>(&smear_lds_kernel<2>);
+        L.grid = dim3((unsigned)grid);
+        L.block = dim3((unsigned)(128 * sh.lds));
+        pack_args(L, job, ln);
+        return L;
+    }
     SmearLaunch ln{};
     ln.site_begin = begin;
     ln.site_count = count;
     ln.interleave = (begin == 0 && count == job.g.V) ? 1 : 0;
+    // zstack = 2 on the whole lattice: both parities in one block (half of
+    // the waves each), single column group
+    const bool mixed = ln.interleave && sh.zstack == 2 && sh.col_groups == 1 && sh.site_waves % 2 == 0;
+    if (mixed) ln.interleave = 2;
+    const int per_parity_waves = mixed ? sh.site_waves / 2 : sh.site_waves;
     // z-stacked blocks: one (x, y) plane of a parity, Lx/2 * Ly sites, in
     // 64-site tiles (rounded)
-    ln.zstride = (sh.zstack && sh.site_waves > 1)
+    ln.zstride = (sh.zstack && per_parity_waves > 1)
                      ? (int32_t)std::max<int64_t>(1, ((int64_t)job.g.Lxh * job.g.L[1] + 32) / 64) : 0;
     const int64_t range = ln.interleave ? job.g.Vh : count;  // sites of one parity's range
     int64_t blocks;
     if (ln.zstride > 0) {
-        const int64_t group = (int64_t)sh.site_waves * ln.zstride;
+        const int64_t group = (int64_t)per_parity_waves * ln.zstride;
         blocks = ((range + 63) / 64 + group - 1) / group * ln.zstride;
     } else {
-        blocks = (range + 64LL * sh.site_waves - 1) / (64LL * sh.site_waves);
+        blocks = (range + 64LL * per_parity_waves - 1) / (64LL * per_parity_waves);
     }
-    ln.nlogical = ln.interleave ? 2 * blocks : blocks;
+    ln.nlogical = ln.interleave == 1 ? 2 * blocks : blocks;
     ln.site_waves = sh.site_waves;
     ln.col_groups = sh.col_groups;
     ln.xcd = sh.xcd;
@@ -531,7 +830,7 @@ Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t 
     } else if (sh.xcd == 2) {
         // a group: the blocks of one z-stack group (both parities' in the
         // interleaved launch), or 8 blocks without z-stacking
-        ln.xcd_group = ln.zstride > 0 ? (ln.interleave ? 2 : 1) * ln.zstride : 8;
+        ln.xcd_group = ln.zstride > 0 ? (ln.interleave == 1 ? 2 : 1) * ln.zstride : 8;
         const int64_t unit = 8LL * ln.xcd_group;
         grid = (grid + unit - 1) / unit * unit;
     }
@@ -543,7 +842,7 @@ Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t 
     return L;
 }
 
-qdp_launch_shape default_shape() { return qdp_launch_shape{4, 1, 1, 2, 0, 0}; }
+qdp_launch_shape default_shape() { return qdp_launch_shape{4, 1, 1, 2, 0, 0, 0}; }
 
 // A candidate launch shape replaces the best one so far only when it is
 // faster by more than 0.5 %.
@@ -599,7 +898,7 @@ qdp_status time_shape(Ctx* ctx, int prec, const SmearJob& job, int64_t begin, in
     float best = 1e30f;
     for (int rep = 0; rep < 5; ++rep) {
         hipEventRecord(e0, ctx->stream);
-        hipLaunchKernel(L.func, L.grid, L.block, p.data(), 0, ctx->stream);
+        hipLaunchKernel(L.func, L.grid, L.block, p.data(), L.shmem, ctx->stream);
         hipEventRecord(e1, ctx->stream);
         hipError_t err = hipEventSynchronize(e1);
         if (err != hipSuccess) {
@@ -641,10 +940,16 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
                 if (sw * cg > 4 || cg > job.ncols) continue;
                 for (int xcd : {0, 1, 2})
                     for (int occ : {0, 2, 3})
-                        for (int zs : {0, 1}) {
+                        for (int zs : {0, 1, 2}) {
                             if ((prec == QDP_F64 && occ) || (zs && sw == 1) || (xcd == 2 && !zs)) continue;
-                            cands.push_back(qdp_launch_shape{sw, cg, xcd, occ, flat, zs});
+                            if (zs == 2 && (count != job.g.V || cg != 1 || sw % 2)) continue;
+                            cands.push_back(qdp_launch_shape{sw, cg, xcd, occ, flat, zs, 0});
                         }
+            }
+        for (int S : {1, 2})
+            for (int xcd : {0, 1}) {
+                const qdp_launch_shape sh{1, 1, xcd, 0, flat, 0, S};
+                if (lds_eligible(prec, job, begin, count, sh)) cands.push_back(sh);
             }
         // two rounds over the candidates, each keeping its faster time, so
         // that no candidate's figure depends on where in the sequence the
@@ -660,9 +965,9 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
         for (size_t i = 0; i < cands.size(); ++i) {
             const qdp_launch_shape& sh = cands[i];
             if (log)
-                std::fprintf(stderr, "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d %d: %.4f ms\n",
+                std::fprintf(stderr, "[qdpmi autotune] prec %d cols %d sites %lld shape %d %d %d %d %d %d %d: %.4f ms\n",
                              prec, job.ncols, (long long)count, sh.site_waves, sh.col_groups, sh.xcd,
-                             sh.waves_per_simd, sh.flat, sh.zstack, t[i]);
+                             sh.waves_per_simd, sh.flat, sh.zstack, sh.lds, t[i]);
             // a later candidate must win by more than the timing noise:
             // equal kernels (the occupancy targets often compile to the same
             // code) keep the first, so the choice repeats run to run
@@ -937,7 +1242,7 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
                     for (int xcd : {0, 1})
                         for (int occ : {0, 2, 3}) {
                             if (sw * cg > 4 || (prec == QDP_F64 && occ)) continue;
-                            const qdp_launch_shape cand{sw, cg, xcd, occ, flat, 0};
+                            const qdp_launch_shape cand{sw, cg, xcd, occ, flat, 0, 0};
                             Launch L = batch_launch(d_first, cand);
                             auto p = arg_pointers(L);
                             float best = 1e30f;

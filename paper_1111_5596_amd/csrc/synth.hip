@@ -67,7 +67,7 @@ __device__ void store_record(char* base, int32_t prec, int32_t nrec, int32_t nco
         for (int k = 0; k < n; ++k)
             *reinterpret_cast<half2_t*>(base + comp_offset(nrec, ncomp, prec, rec, k, s)) =
                 f16s_encode((float)v[k].x, (float)v[k].y, e);
-        *reinterpret_cast<float*>(base + scale_offset(nrec, ncomp, rec, s)) = m > 0.f ? __builtin_ldexpf(1.0f, e) : 1.0f;
+        *reinterpret_cast<float*>(base + scale_offset(nrec, ncomp, rec, s)) = f16s_scale(m, e);
     }
 }
 

@@ -84,7 +84,7 @@ class qdp_cache_stats_t(ctypes.Structure):
 class qdp_launch_shape(ctypes.Structure):
     _fields_ = [("site_waves", ctypes.c_int32), ("col_groups", ctypes.c_int32),
                 ("xcd", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("flat", ctypes.c_int32), ("zstack", ctypes.c_int32)]
+                ("flat", ctypes.c_int32), ("zstack", ctypes.c_int32), ("lds", ctypes.c_int32)]
 
 
 _c = ctypes
@@ -433,19 +433,21 @@ class Context:
             raise ValueError("address outside the pool")
         return self._pool[off:off + nbytes]
 
-    def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0, zstack=0):
+    def set_shape(self, site_waves=0, col_groups=1, xcd=0, waves_per_simd=0, flat=0, zstack=0, lds=0):
         """Force the smearing launch shape (qdp_smear_set_shape; site_waves = 0
         returns to autotuning).  xcd: 0 blocks dealt to the XCDs in turn, 1
         consecutive blocks on one XCD, 2 z-stack groups on one XCD; zstack: the
-        waves of a block take tiles one (x, y) plane apart."""
-        s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, zstack)
+        waves of a block take tiles one (x, y) plane apart; lds = S: whole-
+        lattice F16S updates stage the x/y neighbour window in LDS (blocks of
+        2 S waves)."""
+        s = qdp_launch_shape(site_waves, col_groups, xcd, waves_per_simd, flat, zstack, lds)
         self.check(lib.qdp_smear_set_shape(self.h, ctypes.byref(s)))
 
     def get_shape(self):
-        """(site_waves, col_groups, xcd, waves_per_simd, flat, zstack) of the last smearing call."""
+        """(site_waves, col_groups, xcd, waves_per_simd, flat, zstack, lds) of the last smearing call."""
         s = qdp_launch_shape()
         self.check(lib.qdp_smear_get_shape(self.h, ctypes.byref(s)))
-        return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd, s.flat, s.zstack)
+        return (s.site_waves, s.col_groups, s.xcd, s.waves_per_simd, s.flat, s.zstack, s.lds)
 
     def sync(self):
         self.check(lib.qdp_sync(self.h))
