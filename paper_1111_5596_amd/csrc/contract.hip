@@ -86,12 +86,50 @@ constexpr SignedPerm source_diquark(const SignedPerm& G) {
 }
 constexpr SignedPerm kGamma4 = kGammaBasis[3];
 
-struct GammaDev {
-    int8_t perm[4][4];     // sigma -> spin permutation
-    int8_t members[4][4];  // sigma -> n values
-    int8_t pcode[16][4];   // phase code of P_n[a]: i^code
-    int8_t qcode[16][4];   // phase code of Q_n[b]
+// Gamma_n = gamma_1^b0 gamma_2^b1 gamma_3^b2 gamma_4^b3 (b_k the bits of n)
+constexpr SignedPerm gamma_n(int n) {
+    SignedPerm G{{0, 1, 2, 3}, {0, 0, 0, 0}};
+    for (int k = 0; k < 4; ++k)
+        if (n & (1 << k)) G = sp_mul(G, kGammaBasis[k]);
+    return G;
+}
+
+// The meson contraction's tables, derived at compile time from the signed
+// permutations above: Gamma_n maps spin a to a ^ sigma (sigma = its row 0's
+// column); members[sigma] lists the four n sharing sigma; P_n[a] =
+// s_a Gamma_n[a, a ^ sigma] = i^pcode, Q_n[b] = s_b Gamma_n[b ^ sigma, b] =
+// i^qcode, s = diag(gamma_5) = (1, 1, -1, -1).
+struct MesonTables {
+    int members[4][4];
+    int pcode[16][4];
+    int qcode[16][4];
 };
+constexpr MesonTables make_meson_tables() {
+    MesonTables T{};
+    int count[4] = {0, 0, 0, 0};
+    const int s_code[4] = {0, 0, 2, 2};
+    for (int n = 0; n < 16; ++n) {
+        const SignedPerm G = gamma_n(n);
+        const int sg = G.perm[0];
+        T.members[sg][count[sg]++] = n;
+        for (int a = 0; a < 4; ++a) {
+            T.pcode[n][a] = (G.code[a] + s_code[a]) & 3;
+            T.qcode[n][a] = (G.code[G.perm[a]] + s_code[a]) & 3;
+        }
+    }
+    return T;
+}
+__device__ constexpr MesonTables kMesonTables = make_meson_tables();
+// every Gamma_n permutes spins by an element of the Klein group a -> a ^ sigma
+constexpr bool klein_grouping() {
+    for (int n = 0; n < 16; ++n) {
+        const SignedPerm G = gamma_n(n);
+        for (int a = 0; a < 4; ++a)
+            if (G.perm[a] != (a ^ G.perm[0])) return false;
+    }
+    return true;
+}
+static_assert(klein_grouping(), "DeGrand-Rossi Gamma_n are signed Klein-group permutations");
 
 struct ContractArgs {
     Geometry g;
@@ -125,6 +163,17 @@ struct RawCol<QDP_F16S> {
     }
 };
 
+// re(conj(x) y) + c = x.x y.x + x.y y.y + c and im(conj(x) y) + c =
+// -x.y y.x + x.x y.y + c for half2 x, y: products exact, one FP32 rounding
+// per step (v_dot2_f32_f16; the imaginary part takes (-x.y, x.x), an exact
+// swap and sign change of x).
+__device__ __forceinline__ float dot2_conj_re(half2_t x, half2_t y, float c) {
+    return __builtin_amdgcn_fdot2(x, y, c, false);
+}
+__device__ __forceinline__ float dot2_conj_im(half2_t x, half2_t y, float c) {
+    return __builtin_amdgcn_fdot2(half2_t{(_Float16)(-x.y), x.x}, y, c, false);
+}
+
 // One column at one site: 16-byte chunk loads (3 for F16S, 6 for F32, 12 for
 // F64) and, for F16S, the record scale.
 template <int PREC, bool BUF>
@@ -146,10 +195,14 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// i^code as (re, im), code mod 4.
-__device__ __forceinline__ double2 unit_phase(int code) {
-    code &= 3;
-    return make_double2(code == 0 ? 1.0 : (code == 2 ? -1.0 : 0.0), code == 1 ? 1.0 : (code == 3 ? -1.0 : 0.0));
+// z * i^k (k mod 4): for k known at compile time a swap and signs.
+__device__ __forceinline__ double2 times_ik(double2 z, int k) {
+    switch (k & 3) {
+        case 0: return z;
+        case 1: return make_double2(-z.y, z.x);
+        case 2: return make_double2(-z.x, -z.y);
+        default: return make_double2(z.y, -z.x);
+    }
 }
 
 // exp(-i p.x) for integer momentum k at spatial coordinates c: the phase
@@ -175,13 +228,9 @@ __device__ __forceinline__ double2 plane_wave(const Geometry& g, const int32_t k
 // zero momentum, C[m] accumulates the traces directly; NMOM > 0: a site's
 // traces are complete first, then C[4 q + m] += exp(-i p_q.x) trace_m.
 template <int PREC, bool BUF, int SIGMA, int NMOM>
-__device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDev& gd, int t, int chunk, int lane,
-                                            double2* C) {
+__device__ __forceinline__ void meson_sites(const ContractArgs& A, int t, int chunk, int lane, double2* C) {
     const int64_t Vsh = A.g.Vsh;
     const int64_t Vs = 2 * Vsh;
-    int n[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) n[m] = gd.members[SIGMA][m];
     for (int64_t l = (int64_t)chunk * 64 + lane; l < Vs; l += (int64_t)A.nchunks * 64) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
@@ -189,7 +238,11 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
 #pragma unroll
         for (int m = 0; m < 4; ++m) site_tr[m] = make_double2(0.0, 0.0);
         double2* acc = NMOM > 0 ? site_tr : C;
-        auto source_spin = [&](int beta) {
+        // beta_c: a std::integral_constant (phases folded at compile time)
+        // or, with momenta, a plain int (a rolled loop keeps the registers
+        // of one source spin live at a time)
+        auto source_spin = [&](auto beta_c) {
+            const int beta = beta_c;
             double2 G[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) G[x] = make_double2(0.0, 0.0);
@@ -206,18 +259,25 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 if constexpr (PREC == QDP_F16S) {
-                    // colour sums of the stored half values in FP64 (their
-                    // products are exact), then both record scales at once
-                    // (powers of two: an exact multiply)
+                    // colour sums of the stored half values, conj(a) b summed
+                    // over the three colours by v_dot2 (every product of two
+                    // halves is exact in FP32, each sum rounds once to
+                    // FP32: 2^-24 of the partial sum, which is at most 3 in
+                    // magnitude, so no range is lost); then both record
+                    // scales at once in FP64 (powers of two, the range of
+                    // the smeared propagator) and every sum after in FP64
                     const double sc = (double)c2[b].scale * (double)c1[b].scale;
 #pragma unroll
                     for (int alpha = 0; alpha < 4; ++alpha) {
-                        double2 part = make_double2(0.0, 0.0);
+                        float re = 0.f, im = 0.f;
 #pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            cmac_conj(part, c2[b].stored(3 * alpha + c), c1[b].stored(3 * (alpha ^ SIGMA) + c));
-                        G[alpha].x = fmadd(sc, part.x, G[alpha].x);
-                        G[alpha].y = fmadd(sc, part.y, G[alpha].y);
+                        for (int c = 0; c < 3; ++c) {
+                            const half2_t x = c2[b].h[3 * alpha + c], y = c1[b].h[3 * (alpha ^ SIGMA) + c];
+                            re = dot2_conj_re(x, y, re);
+                            im = dot2_conj_im(x, y, im);
+                        }
+                        G[alpha].x = fmadd(sc, (double)re, G[alpha].x);
+                        G[alpha].y = fmadd(sc, (double)im, G[alpha].y);
                     }
                 } else {
 #pragma unroll
@@ -227,12 +287,17 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
                             cmac_conj(G[alpha], c2[b].at(3 * alpha + c), c1[b].at(3 * (alpha ^ SIGMA) + c));
                 }
             }
+            // C_n += P_n[alpha] Q_n[beta] G[alpha]: a phase i^k known at
+            // compile time, so a swap and signs folded into the additions
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
+                const int n = kMesonTables.members[SIGMA][m];
 #pragma unroll
                 for (int alpha = 0; alpha < 4; ++alpha) {
-                    const double2 ph = unit_phase(gd.pcode[n[m]][alpha] + gd.qcode[n[m]][beta]);
-                    cmac(acc[m], ph, G[alpha]);
+                    const double2 z =
+                        times_ik(G[alpha], kMesonTables.pcode[n][alpha] + kMesonTables.qcode[n][beta]);
+                    acc[m].x += z.x;
+                    acc[m].y += z.y;
                 }
             }
         };
@@ -242,8 +307,10 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
 #pragma unroll 1
             for (int beta = 0; beta < 4; ++beta) source_spin(beta);
         } else {
-#pragma unroll
-            for (int beta = 0; beta < 4; ++beta) source_spin(beta);
+            source_spin(std::integral_constant<int, 0>{});
+            source_spin(std::integral_constant<int, 1>{});
+            source_spin(std::integral_constant<int, 2>{});
+            source_spin(std::integral_constant<int, 3>{});
         }
         if constexpr (NMOM > 0) {
             int32_t c[4];
@@ -259,7 +326,7 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, const GammaDe
 }
 
 template <int PREC, bool BUF, int NMOM>
-__global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd) {
+__global__ __launch_bounds__(256) void meson_kernel(ContractArgs a) {
     constexpr int NQ = NMOM > 0 ? NMOM : 1;
     const int t = blockIdx.y;
     const int chunk = blockIdx.x;
@@ -269,10 +336,10 @@ __global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd)
 #pragma unroll
     for (int m = 0; m < 4 * NQ; ++m) C[m] = make_double2(0.0, 0.0);
     switch (sigma) {
-        case 0: meson_sites<PREC, BUF, 0, NMOM>(a, gd, t, chunk, lane, C); break;
-        case 1: meson_sites<PREC, BUF, 1, NMOM>(a, gd, t, chunk, lane, C); break;
-        case 2: meson_sites<PREC, BUF, 2, NMOM>(a, gd, t, chunk, lane, C); break;
-        default: meson_sites<PREC, BUF, 3, NMOM>(a, gd, t, chunk, lane, C); break;
+        case 0: meson_sites<PREC, BUF, 0, NMOM>(a, t, chunk, lane, C); break;
+        case 1: meson_sites<PREC, BUF, 1, NMOM>(a, t, chunk, lane, C); break;
+        case 2: meson_sites<PREC, BUF, 2, NMOM>(a, t, chunk, lane, C); break;
+        default: meson_sites<PREC, BUF, 3, NMOM>(a, t, chunk, lane, C); break;
     }
     __shared__ double red[4][4 * NQ][2];
 #pragma unroll
@@ -287,7 +354,7 @@ __global__ __launch_bounds__(256) void meson_kernel(ContractArgs a, GammaDev gd)
     __syncthreads();
     if (threadIdx.x < 16 * NQ) {
         const int q = threadIdx.x >> 4, sg = (threadIdx.x >> 2) & 3, m = threadIdx.x & 3;
-        const int n = gd.members[sg][m];
+        const int n = kMesonTables.members[sg][m];
         double* out = a.partial + ((((int64_t)t * a.nchunks + chunk) * NQ + q) * 16 + n) * 2;
         out[0] = red[sg][4 * q + m][0];
         out[1] = red[sg][4 * q + m][1];
@@ -338,15 +405,6 @@ struct BaryonArgs {
     int32_t parity;
 };
 
-// z * i^k for a wave-uniform k.
-__device__ __forceinline__ double2 times_ik(double2 z, int k) {
-    switch (k & 3) {
-        case 0: return z;
-        case 1: return make_double2(-z.y, z.x);
-        case 2: return make_double2(-z.x, -z.y);
-        default: return make_double2(z.y, -z.x);
-    }
-}
 
 // X[r][r'] = component (r, A) of column 3 r' + AP at checkerboard site s.
 // Component 3 r + A lies in chunk (3 r + A) / CE at position (3 r + A) % CE
@@ -612,13 +670,6 @@ void build_gamma_tables(Ctx* ctx) {
 }
 
 namespace {
-int phase_code(const double ph[2]) {
-    if (ph[0] > 0.5) return 0;
-    if (ph[1] > 0.5) return 1;
-    if (ph[0] < -0.5) return 2;
-    return 3;
-}
-
 constexpr int kMomPerLaunch = 4;
 
 template <bool BUF, int NMOM>
@@ -641,7 +692,7 @@ namespace {
 // instead of filling a column from host memory) and fills the kernel
 // arguments shared by the contraction entry points.
 qdp_status meson_setup(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, int32_t j_decay, bool resident_only,
-                       PinSet& pins, ContractArgs* a, GammaDev* gd, int32_t* prec_out) {
+                       PinSet& pins, ContractArgs* a, int32_t* prec_out) {
     if (j_decay != 3) return set_error(ctx, QDP_ERR_UNSUPPORTED, "contract: only j_decay = 3 (time)");
     uint64_t lat = 0;
     int32_t prec = -1;
@@ -680,17 +731,6 @@ qdp_status meson_setup(Ctx* ctx, const uint64_t* S1, const uint64_t* S2, int32_t
         a->s2[c] = p;
     }
     a->nchunks = (int32_t)nchunks;
-
-    for (int sg = 0; sg < 4; ++sg)
-        for (int i = 0; i < 4; ++i) {
-            gd->perm[sg][i] = (int8_t)ctx->gamma.group_perm[sg][i];
-            gd->members[sg][i] = (int8_t)ctx->gamma.group_members[sg][i];
-        }
-    for (int n = 0; n < 16; ++n)
-        for (int i = 0; i < 4; ++i) {
-            gd->pcode[n][i] = (int8_t)phase_code(ctx->gamma.p_phase[n][i]);
-            gd->qcode[n][i] = (int8_t)phase_code(ctx->gamma.q_phase[n][i]);
-        }
     *prec_out = prec;
     return QDP_OK;
 }
@@ -702,12 +742,11 @@ size_t meson_partial_bytes(const ContractArgs& a, int32_t nq) {
 
 // One meson launch (a.partial set, a.mom the launch's momenta) and its
 // fixed-order finish into d_out: nq * 16 * Lt complex values.
-qdp_status meson_launch(Ctx* ctx, ContractArgs& a, const GammaDev& gd, int32_t prec, bool mom, uint32_t mask,
-                        int32_t t0, double* d_out) {
+qdp_status meson_launch(Ctx* ctx, ContractArgs& a, int32_t prec, bool mom, uint32_t mask, int32_t t0,
+                        double* d_out) {
     const int32_t Lt = a.g.L[3];
     const int32_t nq = mom ? kMomPerLaunch : 1;
-    GammaDev gcopy = gd;
-    void* args[] = {&a, &gcopy};
+    void* args[] = {&a};
     const bool buf = field_bytes(a.g, QDP_FERMION, prec) < (int64_t(1) << 32);
     QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)a.nchunks, (unsigned)Lt), dim3(256),
                                  args, 0, ctx->stream));
@@ -724,9 +763,8 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
     if (nmom < 0 || (nmom > 0 && !moms)) return set_error(ctx, QDP_ERR_ARG, "contract: bad momentum list");
     PinSet pins(ctx);
     ContractArgs a;
-    GammaDev gd;
     int32_t prec;
-    QDP_CHECK(meson_setup(ctx, S1, S2, j_decay, false, pins, &a, &gd, &prec));
+    QDP_CHECK(meson_setup(ctx, S1, S2, j_decay, false, pins, &a, &prec));
     const int32_t Lt = a.g.L[3];
     const bool mom = nmom > 0;
     const int32_t nq = mom ? kMomPerLaunch : 1;  // momenta per launch
@@ -745,7 +783,7 @@ qdp_status hadron_contract_impl(Ctx* ctx, const uint64_t* S1, const uint64_t* S2
                 const int32_t k = L * kMomPerLaunch + q;
                 a.mom[q][i] = (mom && k < nmom) ? moms[3 * k + i] : 0;
             }
-        QDP_CHECK(meson_launch(ctx, a, gd, prec, mom, mask, t0, d_out + (size_t)L * nq * 16 * Lt * 2));
+        QDP_CHECK(meson_launch(ctx, a, prec, mom, mask, t0, d_out + (size_t)L * nq * 16 * Lt * 2));
     }
     double* host;
     QDP_CHECK(host_result_buffer(ctx, out_bytes, &host));
@@ -798,16 +836,15 @@ qdp_status hadron_contract_noalloc_impl(Ctx* ctx, const uint64_t* S1, const uint
     if (!ctx->noalloc_scratch) return set_error(ctx, QDP_ERR_STATE, "contract_noalloc: scratch array not set up");
     PinSet pins(ctx);
     ContractArgs a;
-    GammaDev gd;
     int32_t prec;
-    QDP_CHECK(meson_setup(ctx, S1, S2, j_decay, true, pins, &a, &gd, &prec));
+    QDP_CHECK(meson_setup(ctx, S1, S2, j_decay, true, pins, &a, &prec));
     const size_t partial_bytes = meson_partial_bytes(a, 1);
     if (partial_bytes > kNoAllocScratchBytes)
         return set_error(ctx, QDP_ERR_UNSUPPORTED,
                          "contract_noalloc: %zu bytes of partial sums (Lt %d) exceed the %zu-byte scratch array",
                          partial_bytes, a.g.L[3], kNoAllocScratchBytes);
     a.partial = static_cast<double*>(ctx->noalloc_scratch);
-    return meson_launch(ctx, a, gd, prec, false, mask, t0, out_dev);
+    return meson_launch(ctx, a, prec, false, mask, t0, out_dev);
 }
 
 namespace {

@@ -58,32 +58,18 @@ __device__ __forceinline__ float f16s_scale(float m, int e) {
     return m > 0.f ? __builtin_ldexpf(1.0f, e) : kF16sZeroScale;
 }
 
-// a * b + (float)h.x and a * b + (float)h.y in one rounding (v_fma_mix_f32:
-// the half operand is widened exactly inside the instruction).
-__device__ __forceinline__ float fma_mix_lo(float a, float b, half2_t h) {
-    float r;
-    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(a), "v"(b), "v"(h));
-    return r;
-}
-__device__ __forceinline__ float fma_mix_hi(float a, float b, half2_t h) {
-    float r;
-    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(a), "v"(b), "v"(h));
-    return r;
-}
-// max(|a|, |b|, c) in one instruction (c >= 0)
+// a * b + (float)h.x and a * b + (float)h.y in one rounding (the widening
+// of a half is exact; the compiler forms v_fma_mix_f32).
+__device__ __forceinline__ float fma_mix_lo(float a, float b, half2_t h) { return __builtin_fmaf(a, b, (float)h.x); }
+__device__ __forceinline__ float fma_mix_hi(float a, float b, half2_t h) { return __builtin_fmaf(a, b, (float)h.y); }
+// max(|a|, |b|, c) (v_max3_f32)
 __device__ __forceinline__ float max3_abs(float a, float b, float c) {
-    float r;
-    asm("v_max3_f32 %0, |%1|, |%2|, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
+    return __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(a), __builtin_fabsf(b)), c);
 }
-// (half(x * s), half(y * s)) with one rounding each (v_fma_mixlo_f16 /
-// v_fma_mixhi_f16 with a zero addend); for s a power of two the products are
-// exact, so this is the round-to-nearest-even FP16 of x * s and y * s.
+// (half(x * s), half(y * s)); for s a power of two the products are exact,
+// so this is the round-to-nearest-even FP16 of x * s and y * s.
 __device__ __forceinline__ half2_t mul_to_half2(float x, float y, float s) {
-    half2_t r;
-    asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(r) : "v"(x), "v"(s));
-    asm("v_fma_mixhi_f16 %0, %1, %2, 0" : "+v"(r) : "v"(y), "v"(s));
-    return r;
+    return half2_t{(_Float16)(x * s), (_Float16)(y * s)};
 }
 
 __device__ __forceinline__ half2_t f16s_encode(float re, float im, int e) {
@@ -96,6 +82,11 @@ __device__ __forceinline__ half2_t f16s_encode(float re, float im, int e) {
 __device__ __forceinline__ float2 f16s_decode(half2_t q, float scale) {
     return make_float2((float)q.x * scale, (float)q.y * scale);
 }
+
+// These are plain code rather than inline assembly on purpose: the compiler
+// inserts the wait states a VALU instruction needs after a v_dot2 that wrote
+// one of its sources only for instructions it generated itself, not for
+// inline assembly.
 
 // Raw buffer access: one 128-bit resource per field (base address, no
 // stride, full 32-bit range), a per-lane byte offset in a VGPR shared by all
@@ -298,14 +289,8 @@ __device__ __forceinline__ int64_t site_off(int32_t site, int64_t tb) {
     return (int64_t)(site >> 6) * tb + (int64_t)(site & 63) * (int64_t)sizeof(T);
 }
 
-// v_dot2_f32_f16 with a zero accumulator as an inline constant: the
-// compiler otherwise materialises the zero with a move to use the
-// accumulating two-operand form.
-__device__ __forceinline__ float dot2_zero(half2_t a, half2_t b) {
-    float r;
-    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
+// a.x b.x + a.y b.y in FP32 (v_dot2_f32_f16 with a zero accumulator)
+__device__ __forceinline__ float dot2_zero(half2_t a, half2_t b) { return __builtin_amdgcn_fdot2(a, b, 0.f, false); }
 
 // Neighbour indices of a checkerboard site in the three spatial directions.
 struct SpatialNeighbours {

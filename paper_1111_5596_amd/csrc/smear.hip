@@ -146,15 +146,11 @@ __device__ __forceinline__ void site_update_real(const SmearJob& job, int32_t s,
 // Per-site update, F16S storage (FP32 arithmetic)
 // ---------------------------------------------------------------------------
 
-// Always the VOP3P v_dot2_f32_f16 (inline asm): left to the compiler, the
-// accumulating form is emitted as the VOP2 v_dot2c_f32_f16 or as the VOP3P
-// instruction depending on register allocation, and the two need not agree
-// on subnormal half inputs, which would make launch shapes differ in bits.
-__device__ __forceinline__ float dot2(half2_t a, half2_t b, float c) {
-    float r;
-    asm("v_dot2_f32_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
+// a.x b.x + a.y b.y + c in FP32 (v_dot2_f32_f16 or its two-operand form
+// v_dot2c_f32_f16, the same operation).  Never inline assembly: a VALU
+// instruction that reads a v_dot2 result needs wait states after it, which
+// the compiler inserts only for instructions it generated itself.
+__device__ __forceinline__ float dot2(half2_t a, half2_t b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
 
 // The F16S update of one site and column, shared by every kernel variant so
 // that all of them produce the same bits.  The six hop terms are taken in the

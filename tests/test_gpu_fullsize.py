@@ -51,17 +51,20 @@ def test_48cubed_96_smear_and_contract(qdp, prec):
         S = np.stack([qdp.read_timeslices(f, t, t + 1) for f in out])
         Cref = oracle.meson(S, S, sd)[:, 0]
         scale = abs(Cref[15].real)
-        assert np.max(np.abs(C[:, t] - Cref)) <= 1e-10 * scale
+        # F16S: FP32 colour sums of exact products of the stored halves
+        assert np.max(np.abs(C[:, t] - Cref)) <= (2e-6 if prec == "F16S" else 1e-10) * scale
         # properties on every slice: C_15 > 0 real, |C_n| <= C_15, Im C_n ~ 0
         c15 = C[15].real
         assert np.all(c15 > 0)
-        assert np.all(np.abs(C) <= c15[None, :] * (1 + 1e-9))
-        assert np.max(np.abs(C.imag)) <= 1e-9 * c15.max()
+        eps = 2e-6 if prec == "F16S" else 1e-9
+        assert np.all(np.abs(C) <= c15[None, :] * (1 + eps))
+        assert np.max(np.abs(C.imag)) <= eps * c15.max()
         # FP64 time-slice sums of |psi|^2 agree with C_15
         n2 = np.zeros(dims[3])
         for f in out:
             n2 += qdp.sum_multi([("field", f), ("local_norm2",)], "timeslice", 1, dims[3])[:, 0].real
-        assert np.max(np.abs(n2 - c15) / c15) <= 1e-9
+        # F16S: C_15 from FP32 colour sums of the stored halves
+        assert np.max(np.abs(n2 - c15) / c15) <= (2e-6 if prec == "F16S" else 1e-9)
     finally:
         for f in [g] + src + out:
             qdp.free(f)
@@ -242,7 +245,8 @@ def test_48cubed_96_hadron_contractions_sampled(qdp):
         moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
         got = qdp.contract_mom(cols, cols, moms)[:, :, t]
         ref = oracle.meson_mom(S, S, sd, moms)[:, :, 0]
-        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+        # FP32 colour sums of exact products of the stored halves, FP64 after
+        assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
         for parity in (1, -1):
             got = qdp.nucleon(cols, cols, parity=parity)[t]
             ref = oracle.nucleon(S, S, sd, parity)[0]
