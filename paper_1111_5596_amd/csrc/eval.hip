@@ -38,6 +38,7 @@ enum NodeOp : int32_t {
     K_NEG = 0, K_CONJ, K_ADJ, K_TRACE, K_TRACE_COLOR, K_TRACE_SPIN, K_REAL, K_IMAG, K_NORM2,
     K_GAMMA_L, K_GAMMA_R, K_COPY,  // unary
     K_ADD, K_SUB, K_MUL, K_INNER,  // binary
+    K_TRACE_MUL,                   // binary, formed by the lowering: trace(a b)
     K_NUM_OPS
 };
 constexpr int kNumTypes = 7;  // REAL .. PROPAGATOR
@@ -105,6 +106,8 @@ constexpr int result_type(int op, int a, int b) {
          : op == K_ADD || op == K_SUB ? (a == b ? a : (is_scalar(a) && is_scalar(b)) ? QDP_COMPLEX : -1)
          : op == K_MUL   ? mul_type(a, b)
          : op == K_INNER ? (a == b ? QDP_COMPLEX : -1)
+         : op == K_TRACE_MUL ? ((a == b && (a == QDP_COLOR_MATRIX || a == QDP_SPIN_MATRIX || a == QDP_PROPAGATOR))
+                                    ? QDP_COMPLEX : -1)
                          : -1;
 }
 
@@ -367,6 +370,15 @@ __device__ __forceinline__ void apply_op(const NodeArgs& A, const cplx_t<R>* a, 
         T2 acc{0, 0};
         for (int k = 0; k < NA; ++k) cmac_conj(acc, a[k], b[k]);
         r[0] = acc;
+    } else if constexpr (OP == K_TRACE_MUL) {
+        // Tr(a b) = sum a[i][k][x][z] b[k][i][z][x] (a, b square, one type)
+        using I = Idx<sa.s1, sa.s2, sa.c1, sa.c2>;
+        T2 acc{0, 0};
+        for (int i = 0; i < sa.s1; ++i)
+            for (int k = 0; k < sa.s2; ++k)
+                for (int x = 0; x < sa.c1; ++x)
+                    for (int z = 0; z < sa.c2; ++z) cmac(acc, a[I::at(i, k, x, z)], b[I::at(k, i, z, x)]);
+        r[0] = acc;
     } else if constexpr (OP == K_GAMMA_L) {
         using I = Idx<sa.s1, sa.s2, sa.c1, sa.c2>;
         const int n = A.gamma_n;
@@ -476,6 +488,22 @@ const KernelTable& kernel_table() {
     return table;
 }
 
+// Local-reduction kernels: [op][operand type] for the ops formed inside a
+// reduction.
+struct LocalReduceTable {
+    void* k[K_NUM_OPS][kNumTypes];
+};
+
+template <int OP, int TA>
+void fill_local(LocalReduceTable& t);
+
+template <int OP, int... TA>
+void fill_local_ta(LocalReduceTable& t, std::integer_sequence<int, TA...>) {
+    (fill_local<OP, TA>(t), ...);
+}
+
+const LocalReduceTable& local_reduce_table();
+
 // ---------------------------------------------------------------------------
 // Fused stencil kernel: dest(x) = sum_k c_k [adj] M_k(x + d_k) V_k(x + e_k)
 // ---------------------------------------------------------------------------
@@ -564,37 +592,106 @@ __device__ __forceinline__ void set_subset(const Geometry& g, int32_t set, int32
     else *d = SubsetDesc{QDP_TIMESLICE, sub, 2 * g.Vsh};
 }
 
-__device__ __forceinline__ double block_sum(double v, double* lds) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum of NV complex values over the block's threads (wave shuffles, then
+// the four waves in a fixed order); thread v < NV of wave 0 ends with value v.
+template <int NV>
+__device__ __forceinline__ void block_sum_values(double2 v[NV], double* lds /* [4][NV][2] */, double2* out) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            v[j].x += __shfl_xor(v[j].x, off, 64);
+            v[j].y += __shfl_xor(v[j].y, off, 64);
+        }
+        if (lane == 0) {
+            lds[(w * NV + j) * 2] = v[j].x;
+            lds[(w * NV + j) * 2 + 1] = v[j].y;
+        }
+    }
     __syncthreads();
-    if (lane == 0) lds[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += lds[i];
-    return r;
+    if ((int)threadIdx.x < NV) {
+        const int j = threadIdx.x;
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            re += lds[(i * NV + j) * 2];
+            im += lds[(i * NV + j) * 2 + 1];
+        }
+        *out = make_double2(re, im);
+    }
 }
 
+// Per-component sums of a field, one thread per site and NV components
+// (group blockIdx.z of the record: components z NV .. z NV + NV - 1), so a
+// site's record is read once; FP64.
+template <int NV>
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs A) {
-    const int chunk = blockIdx.x, sub = blockIdx.y, k = blockIdx.z;
+    const int chunk = blockIdx.x, sub = blockIdx.y, k0 = blockIdx.z * NV;
     SubsetDesc d;
     set_subset(A.g, A.set, sub, &d);
-    double re = 0.0, im = 0.0;
+    double2 acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = make_double2(0.0, 0.0);
     for (int64_t l = (int64_t)chunk * blockDim.x + threadIdx.x; l < d.count; l += (int64_t)A.nchunks * blockDim.x) {
         const int32_t s = (int32_t)subset_site(A.g, d, l);
-        const double2 v = load_comp<double>(A.base, A.prec, A.nrec, A.ncomp, 0, k, s);
-        re += v.x;
-        im += v.y;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            if (k0 + j < A.ncomp) {
+                const double2 v = load_comp<double>(A.base, A.prec, A.nrec, A.ncomp, 0, k0 + j, s);
+                acc[j].x += v.x;
+                acc[j].y += v.y;
+            }
+        }
     }
-    __shared__ double lds[16];
-    const double r0 = block_sum(re, lds);
-    const double r1 = block_sum(im, lds);
+    __shared__ double lds[4 * NV * 2];
+    double2 r;
+    block_sum_values<NV>(acc, lds, &r);
+    if ((int)threadIdx.x < NV && k0 + (int)threadIdx.x < A.ncomp) {
+        double* p = A.partial + (((int64_t)sub * A.nchunks + chunk) * A.ncomp + k0 + threadIdx.x) * 2;
+        p[0] = r.x;
+        p[1] = r.y;
+    }
+}
+
+// Sums of a site-local scalar formed inside the reduction: OP = K_NORM2
+// (sum |a|^2), K_INNER (sum a^dagger b), K_TRACE (trace a) or K_TRACE_MUL
+// (trace a b) of operands of type TA, each read once at the sites of the set;
+// no intermediate field.  FP64.
+struct LocalReduceArgs {
+    Geometry g;
+    Operand a, b;
+    int32_t set, nchunks;
+    int32_t need_coords, pad;
+    double* partial;  // [nsub][nchunks][1][2]
+};
+
+template <int OP, int TA>
+__global__ __launch_bounds__(256) void reduce_local_kernel(LocalReduceArgs A) {
+    constexpr int TB = is_binary(OP) ? TA : 0;
+    constexpr int NA = ncomp_of(TA), NB = is_binary(OP) ? ncomp_of(TB) : 1;
+    const int chunk = blockIdx.x, sub = blockIdx.y;
+    SubsetDesc d;
+    set_subset(A.g, A.set, sub, &d);
+    const NodeArgs none{};
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int64_t l = (int64_t)chunk * blockDim.x + threadIdx.x; l < d.count; l += (int64_t)A.nchunks * blockDim.x) {
+        const int32_t s = (int32_t)subset_site(A.g, d, l);
+        int32_t c[4] = {0, 0, 0, 0};
+        if (A.need_coords) cb_coords(A.g, s, c);
+        double2 a[NA], b[NB], r[1];
+        load_operand<TA, double>(A.a, A.g, s, c, a);
+        if constexpr (is_binary(OP)) load_operand<TB, double>(A.b, A.g, s, c, b);
+        apply_op<OP, TA, TB, double>(none, a, b, r);
+        acc[0].x += r[0].x;
+        acc[0].y += r[0].y;
+    }
+    __shared__ double lds[8];
+    double2 r;
+    block_sum_values<1>(acc, lds, &r);
     if (threadIdx.x == 0) {
-        double* p = A.partial + (((int64_t)sub * A.nchunks + chunk) * A.ncomp + k) * 2;
-        p[0] = r0;
-        p[1] = r1;
+        double* p = A.partial + ((int64_t)sub * A.nchunks + chunk) * 2;
+        p[0] = r.x;
+        p[1] = r.y;
     }
 }
 
@@ -611,6 +708,26 @@ __global__ void reduce_finish(const double* __restrict__ partial, int32_t nsub, 
     }
     out[idx * 2] = re;
     out[idx * 2 + 1] = im;
+}
+
+template <int OP, int TA>
+void fill_local(LocalReduceTable& t) {
+    constexpr int TB = is_binary(OP) ? TA : 0;
+    if constexpr (result_type(OP, TA, TB) == QDP_REAL || result_type(OP, TA, TB) == QDP_COMPLEX)
+        t.k[OP][TA] = reinterpret_cast<void*>(&reduce_local_kernel<OP, TA>);
+}
+
+const LocalReduceTable& local_reduce_table() {
+    static LocalReduceTable table = [] {
+        LocalReduceTable t;
+        std::memset(&t, 0, sizeof t);
+        fill_local_ta<K_NORM2>(t, std::make_integer_sequence<int, kNumTypes>{});
+        fill_local_ta<K_INNER>(t, std::make_integer_sequence<int, kNumTypes>{});
+        fill_local_ta<K_TRACE>(t, std::make_integer_sequence<int, kNumTypes>{});
+        fill_local_ta<K_TRACE_MUL>(t, std::make_integer_sequence<int, kNumTypes>{});
+        return t;
+    }();
+    return table;
 }
 
 // ---------------------------------------------------------------------------
@@ -877,6 +994,14 @@ qdp_status temp_operand(Lowering& L, int type, int prec, Operand* op, OutDesc* o
 }
 
 // Evaluate node n into `out` (a temporary or the destination).
+// trace(a b) of two square matrices of one type (colour, spin or
+// propagator): evaluated as one node, Tr(a b) = sum a_ij b_ji.
+bool is_trace_of_product(const Node& n) {
+    if (n.op != K_TRACE || !n.a || n.a->op != K_MUL) return false;
+    const Node& m = *n.a;
+    return result_type(K_TRACE_MUL, m.a->type, m.b->type) >= 0;
+}
+
 qdp_status emit(Lowering& L, const Node& n, const SubsetDesc& sub, const OutDesc& out, int cprec) {
     NodeArgs A;
     std::memset(&A, 0, sizeof A);
@@ -889,6 +1014,12 @@ qdp_status emit(Lowering& L, const Node& n, const SubsetDesc& sub, const OutDesc
     const Node* nb = nullptr;
     if (is_leaf(n)) {
         op = K_COPY;
+    } else if (is_trace_of_product(n)) {
+        // trace(a b) in one kernel: no product field in between
+        op = K_TRACE_MUL;
+        na = n.a->a.get();
+        nb = n.a->b.get();
+        ta = tb = na->type;
     } else {
         na = n.a.get();
         nb = n.b.get();
@@ -1052,21 +1183,6 @@ qdp_status sum_multi_impl(Ctx* ctx, const qdp_expr* expr, int32_t set, double* o
     R.ncomp = ts.ncomp;
     R.nrec = ts.nrec;
     R.set = set;
-    if (root->op == -1 && !has_disp(*root) && find_field(ctx, root->field)->type == root->type) {
-        // a bare field: reduce it in place
-        Operand o;
-        QDP_CHECK(leaf_operand(L, *root, &o));
-        R.base = o.base;
-        R.prec = o.prec;
-    } else {
-        // evaluate the expression in FP64 over all sites into a temporary
-        Operand o;
-        OutDesc tmp;
-        QDP_CHECK(temp_operand(L, type, QDP_F64, &o, &tmp));
-        QDP_CHECK(emit(L, *root, SubsetDesc{QDP_ALL, 0, g.V}, tmp, QDP_F64));
-        R.base = o.base;
-        R.prec = QDP_F64;
-    }
     int64_t per_sub = set == QDP_SET_ALL ? g.V : set == QDP_SET_PARITY ? g.Vh : 2 * g.Vsh;
     int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>((per_sub + 255) / 256, 1024 / nsub + 1));
     R.nchunks = (int32_t)nchunks;
@@ -1075,10 +1191,71 @@ qdp_status sum_multi_impl(Ctx* ctx, const qdp_expr* expr, int32_t set, double* o
     QDP_CHECK(scratch.alloc(ctx, (int64_t)(partial_bytes + need * sizeof(double) + 256)));
     R.partial = reinterpret_cast<double*>(scratch.ptr());
     double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
-    void* args[] = {&R};
-    QDP_HIP(ctx, hipLaunchKernel(reinterpret_cast<void*>(&reduce_kernel), dim3((unsigned)nchunks, nsub, ts.ncomp),
-                                 dim3(256), args, 0, ctx->stream));
-    QDP_CHECK(check_launch(ctx, "reduce kernel"));
+
+    // a site-local scalar (|a|^2, a^dagger b, trace a, trace a b) is formed
+    // inside the reduction, its operands evaluated first only if they are
+    // not fields
+    int lop = -1, lta = 0;
+    const Node *la = nullptr, *lb = nullptr;
+    if (is_trace_of_product(*root)) {
+        lop = K_TRACE_MUL;
+        la = root->a->a.get();
+        lb = root->a->b.get();
+    } else if (root->op == K_NORM2 || root->op == K_INNER || root->op == K_TRACE) {
+        lop = root->op;
+        la = root->a.get();
+        lb = root->b.get();
+    }
+    if (la) lta = la->type;
+    void* lfn = lop >= 0 ? local_reduce_table().k[lop][lta] : nullptr;
+    if (lfn) {
+        LocalReduceArgs LA;
+        std::memset(&LA, 0, sizeof LA);
+        LA.g = g;
+        LA.set = set;
+        LA.nchunks = (int32_t)nchunks;
+        LA.partial = R.partial;
+        auto operand = [&](const Node& c, Operand* o) -> qdp_status {
+            if (is_leaf(c)) return leaf_operand(L, c, o);
+            OutDesc tmp;
+            QDP_CHECK(temp_operand(L, c.type, QDP_F64, o, &tmp));
+            return emit(L, c, SubsetDesc{QDP_ALL, 0, g.V}, tmp, QDP_F64);
+        };
+        QDP_CHECK(operand(*la, &LA.a));
+        if (lb) QDP_CHECK(operand(*lb, &LA.b));
+        LA.need_coords = LA.a.has_disp || (lb && LA.b.has_disp);
+        void* args[] = {&LA};
+        QDP_HIP(ctx, hipLaunchKernel(lfn, dim3((unsigned)nchunks, nsub, 1), dim3(256), args, 0, ctx->stream));
+        QDP_CHECK(check_launch(ctx, "local reduce kernel"));
+    } else {
+        if (root->op == -1 && !has_disp(*root) && find_field(ctx, root->field)->type == root->type) {
+            // a bare field: reduce it in place
+            Operand o;
+            QDP_CHECK(leaf_operand(L, *root, &o));
+            R.base = o.base;
+            R.prec = o.prec;
+        } else {
+            // evaluate the expression in FP64 over all sites into a temporary
+            Operand o;
+            OutDesc tmp;
+            QDP_CHECK(temp_operand(L, type, QDP_F64, &o, &tmp));
+            QDP_CHECK(emit(L, *root, SubsetDesc{QDP_ALL, 0, g.V}, tmp, QDP_F64));
+            R.base = o.base;
+            R.prec = QDP_F64;
+        }
+        // one thread per site and up to 16 components (propagators: nine
+        // groups, each reading its part of the record)
+        const int nv = ts.ncomp <= 16 ? ts.ncomp : 16;
+        const int ngroups = (ts.ncomp + nv - 1) / nv;
+        void* fn = nv == 1 ? reinterpret_cast<void*>(&reduce_kernel<1>)
+                 : nv == 3 ? reinterpret_cast<void*>(&reduce_kernel<3>)
+                 : nv == 9 ? reinterpret_cast<void*>(&reduce_kernel<9>)
+                 : nv == 12 ? reinterpret_cast<void*>(&reduce_kernel<12>)
+                            : reinterpret_cast<void*>(&reduce_kernel<16>);
+        void* args[] = {&R};
+        QDP_HIP(ctx, hipLaunchKernel(fn, dim3((unsigned)nchunks, nsub, ngroups), dim3(256), args, 0, ctx->stream));
+        QDP_CHECK(check_launch(ctx, "reduce kernel"));
+    }
     const int nt = nsub * ts.ncomp;
     hipLaunchKernelGGL(reduce_finish, dim3((nt + 255) / 256), dim3(256), 0, ctx->stream, R.partial, nsub,
                        (int32_t)nchunks, ts.ncomp, d_out);

@@ -82,6 +82,8 @@ PROGRAMS = [
     ("REAL", [("field", "c"), ("real",), ("field", "r"), ("shift", 1, -1), ("mul",)]),
     ("COLOR_VECTOR", [("field", "A"), ("field", "v"), ("mul",), ("field", "w"), ("shift", 0, 1), ("sub",)]),
     ("COMPLEX", [("field", "A"), ("trace",), ("real_const", 2.0), ("mul",)]),
+    ("COMPLEX", [("field", "A"), ("field", "B"), ("shift", 0, 1), ("mul",), ("trace",)]),
+    ("COMPLEX", [("field", "M"), ("field", "M"), ("gamma_left", 5), ("mul",), ("trace",)]),
 ]
 
 
@@ -212,16 +214,50 @@ def test_alias_and_type_errors(env):
 @pytest.mark.parametrize("kind,nsub", [("all", 1), ("parity", 2), ("timeslice", DIMS[3])])
 def test_sum_multi(env, kind, nsub):
     q, lat, host, handles = env
+    # the first six are formed inside the reduction (local norm, inner
+    # product, trace, trace of a product; shifted, and an evaluated operand),
+    # the others reduce a field or an evaluated temporary component-wise
     for t, prog in [("REAL", [("field", "psi"), ("local_norm2",)]),
                     ("COMPLEX", [("field", "P"), ("field", "Q"), ("mul",), ("trace",)]),
+                    ("COMPLEX", [("field", "psi"), ("field", "chi"), ("shift", 1, -1), ("local_inner",)]),
+                    ("COMPLEX", [("field", "A"), ("shift", 3, 1), ("trace",)]),
+                    ("REAL", [("field", "psi"), ("field", "chi"), ("sub",), ("local_norm2",)]),
+                    ("COMPLEX", [("field", "A"), ("field", "B"), ("adj",), ("mul",), ("trace",)]),
                     ("COLOR_MATRIX", [("field", "A")]),
+                    ("PROPAGATOR", [("field", "P")]),
+                    ("SPIN_MATRIX", [("field", "P"), ("trace_color",)]),
                     ("FERMION", [("gauge", "U", 2), ("field", "psi"), ("shift", 2, 1), ("mul",)])]:
-        ncomp = {"REAL": 1, "COMPLEX": 1, "COLOR_MATRIX": 9, "FERMION": 12}[t]
+        ncomp = {"REAL": 1, "COMPLEX": 1, "COLOR_MATRIX": 9, "FERMION": 12, "PROPAGATOR": 144,
+                 "SPIN_MATRIX": 16}[t]
         got = q.sum_multi(to_gpu(prog, handles), kind, ncomp, nsub)
         _, expect = E.sum_multi(prog, host, DIMS, kind)
         assert np.abs(got - expect).max() <= 1e-12 * np.abs(expect).max()
         got2 = q.sum_multi(to_gpu(prog, handles), kind, ncomp, nsub)
         assert np.array_equal(got, got2)
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16S"])
+def test_local_reductions_of_stored_fields(qdp, prec):
+    """|psi|^2 and psi^dagger chi formed inside the reduction from FP32 and
+    F16S fields, every slice: FP64 sums of the decoded stored values."""
+    dims = (6, 4, 4, 6)
+    lat = qdp.lattice(dims)
+    psi, chi = synth.gaussian_propagator(dims, 131, ncols=2)
+    a, b = qdp.alloc(lat, "FERMION", prec), qdp.alloc(lat, "FERMION", prec)
+    qdp.write(a, psi)
+    qdp.write(b, chi)
+    pa, pb = qdp.read(a), qdp.read(b)
+    vs = dims[0] * dims[1] * dims[2]
+    n2 = qdp.sum_multi([("field", a), ("local_norm2",)], "timeslice", 1, dims[3])[:, 0]
+    ip = qdp.sum_multi([("field", a), ("field", b), ("local_inner",)], "timeslice", 1, dims[3])[:, 0]
+    for t in range(dims[3]):
+        sl = slice(t * vs, (t + 1) * vs)
+        e_n2 = np.sum(np.abs(pa[sl]) ** 2)
+        e_ip = np.sum(np.conj(pa[sl]) * pb[sl])
+        assert abs(n2[t] - e_n2) <= 1e-13 * e_n2 and n2[t].imag == 0
+        assert abs(ip[t] - e_ip) <= 1e-13 * e_n2
+    qdp.free(a)
+    qdp.free(b)
 
 
 @pytest.mark.parametrize("prec", ["F32", "F64", "F16S"])
