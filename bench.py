@@ -468,7 +468,7 @@ def oracle_leg(res):
     import oracle
     from paper_1111_5596_amd import synth
 
-    errs = {}
+    errs, per_config = {}, {}
     # config 5: slice 0 of the headline workload, N = 100 (timed)
     sd = (48, 48, 48, 1)
     U = synth.su3_links(DIMS, LINK_SEED, t_range=(0, 1))
@@ -499,7 +499,10 @@ def oracle_leg(res):
         d1 = (4, 4, 4, 8)
         U1 = synth.su3_links(d1, 1)
         p1 = synth.point_source(d1, [0])
+        t0 = time.perf_counter()
         s1 = oracle.smear(U1, p1, d1, KAPPA, 10)[0]
+        per_config["c1_4c8"] = {"value": volume(d1) * 10 / (time.perf_counter() - t0),
+                                "sample": "whole lattice, 1 column, N = 10"}
         C1 = np.array([np.sum(np.abs(s1[t * 64:(t + 1) * 64]) ** 2) for t in range(8)])
         errs["c1_4c8"] = {prec: {"field_relL2": relerr(r["psi"], s1),
                                  "C_rel": float(np.max(np.abs(r["C"] - C1)) / C1[0]),
@@ -512,9 +515,14 @@ def oracle_leg(res):
             continue
         sdim = dims[:3] + (1,)
         Us = synth.su3_links(dims, seed, t_range=(0, 1))
+        Ps = synth.gaussian_propagator(dims, 100 + seed, t_range=(0, 1))
+        t0 = time.perf_counter()
         src = oracle.smear(Us, synth.point_source(sdim), sdim, KAPPA, n)
-        snk = oracle.smear(Us, synth.gaussian_propagator(dims, 100 + seed, t_range=(0, 1)), sdim, KAPPA, n)
+        snk = oracle.smear(Us, Ps, sdim, KAPPA, n)
         Cs = oracle.meson(snk, snk, sdim)
+        per_config[f"{key}_{dims[0]}c{dims[3]}"] = {
+            "value": 2 * 12 * volume(sdim) * n / (time.perf_counter() - t0),
+            "sample": f"time slice 0: SRC + SNK smearing (2 x 12 columns, N = {n}) + one 16-bilinear contraction"}
         runs = {"F32": r["batched"]} if key == "c2" else {p: r[p] for p in ("F16S", "F32")}
         if key == "c2":
             runs["F32"] = dict(runs["F32"], src_slice0=r["src_slice0"], snk_slice0=r["snk_slice0"], C=r["C"])
@@ -532,10 +540,14 @@ def oracle_leg(res):
     if b:
         c15_err, field_err = 0.0, 0.0
         cache = {}
+        t_c4, u_c4 = 0.0, 0
         for l, dims in enumerate(b["sizes"]):
             sdim = dims[:3] + (1,)
             Ul = synth.su3_links(dims, 4001 + l, t_range=(0, 1))
+            t0 = time.perf_counter()
             Sl = oracle.smear(Ul, synth.point_source(sdim), sdim, KAPPA, 30)
+            t_c4 += time.perf_counter() - t0
+            u_c4 += 12 * volume(sdim) * 30
             c15 = float(np.sum(np.abs(Sl) ** 2))
             c15_err = max(c15_err, abs(b["C15"][l][0] - c15) / c15)
             if l in b["slices"]:
@@ -544,6 +556,10 @@ def oracle_leg(res):
         zeros = all(np.all(np.asarray(c)[1:] == 0) for c in b["C15"])
         errs["c4_batch64"] = {"C15_t0_rel_max_over_64": c15_err, "field_relL2_sampled": field_err,
                               "zeros_off_source_slice_exact": bool(zeros)}
+        per_config["c4_batch64"] = {"value": u_c4 / t_c4,
+                                    "sample": "time slice 0 of each of the 64 lattices, 12 columns, N = 30"}
+    if per_config:
+        base["per_config"] = per_config
     return base, errs
 
 
@@ -559,7 +575,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the 4^3x8, 16^3x32 and 24^3x48 workloads")
     ap.add_argument("--no-two-pass", action="store_true", help="skip the two-launch even/odd variant")
     ap.add_argument("--shape", default=None,
-                    help="force the smearing launch shape site_waves,col_groups,xcd,waves_per_simd,flat,zstack "
+                    help="force the smearing launch shape site_waves,col_groups,xcd,waves_per_simd,flat,zstack[,lds] "
                          "instead of autotuning (for profiler runs that must repeat a measured shape)")
     args = ap.parse_args()
     if args.gpus != 1:

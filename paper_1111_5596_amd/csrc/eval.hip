@@ -1184,7 +1184,9 @@ qdp_status sum_multi_impl(Ctx* ctx, const qdp_expr* expr, int32_t set, double* o
     R.nrec = ts.nrec;
     R.set = set;
     int64_t per_sub = set == QDP_SET_ALL ? g.V : set == QDP_SET_PARITY ? g.Vh : 2 * g.Vsh;
-    int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>((per_sub + 255) / 256, 1024 / nsub + 1));
+    // enough blocks to keep every CU's memory pipeline busy (about 16 waves
+    // per CU over all subsets), each thread then walking its chunk's sites
+    int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>((per_sub + 255) / 256, 4096 / nsub + 1));
     R.nchunks = (int32_t)nchunks;
     PoolTemp scratch;
     const size_t partial_bytes = sizeof(double) * 2 * (size_t)nsub * nchunks * ts.ncomp;

@@ -50,7 +50,7 @@ def test_traffic_record_parses_and_is_keyed_to_the_kernel():
     assert (bench.measured_traffic(mode=mode) is None) == stale
     # and only for the launch shape and mode it was measured with
     shape = tuple(int(x) for x in rec["launch_shape_tuple"].split(","))
-    assert len(shape) == 6
+    assert len(shape) == 7
     assert (bench.measured_traffic(shape, mode) is None) == stale
     other = (shape[0] % 4 + 1,) + shape[1:]
     assert bench.measured_traffic(other, mode) is None
