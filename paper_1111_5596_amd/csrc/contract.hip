@@ -10,10 +10,12 @@
 //   G_sigma[a][b] = sum_{i,j colour} conj(S2[(a i),(b j)]) S1[(sigma a, i),(sigma b, j)]
 //
 // and C_n = sum_{a,b} P_n[a] Q_n[b] G_sigma[a][b] with P_n[a] = s_a Gamma_n[a, sigma a],
-// Q_n[b] = s_b Gamma_n[sigma b, b], s = diag(g5).  One wavefront of a block
-// handles one sigma for 64 sites; the four wavefronts read the same sites.
-// Momentum projection weights each site's traces by exp(-i p.x) before the
-// slice sum; one launch carries up to four momenta.
+// Q_n[b] = s_b Gamma_n[sigma b, b], s = diag(g5).  Zero-momentum F16S
+// contractions run one wavefront per source colour (each column of a site
+// read once per block); the other precisions and the momentum-projected
+// contractions run one wavefront per sigma, the four wavefronts of a block
+// reading the same 64 sites.  Momentum projection weights each site's traces
+// by exp(-i p.x) before the slice sum; one launch carries up to four momenta.
 // Products and sums are FP64 (propagators grow like 2^N under smearing and
 // |S|^2 leaves the FP32 range).  The time-slice sums are two-stage with a
 // fixed order: bitwise repeatable.
@@ -361,6 +363,171 @@ __global__ __launch_bounds__(256) void meson_kernel(ContractArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Zero-momentum F16S contraction, one wavefront per source colour
+// ---------------------------------------------------------------------------
+// Within a Klein coset the four bilinears differ only by signs that depend on
+// a ^ b: P_n[a] Q_n[b] = B_sigma[a][b] f_n(a ^ b), B_sigma the phases of the
+// coset's first member and f_n(k) = +1 or -1 (checked at compile time).  So
+// the slice sum needs only H_sigma[k] = sum_{a ^ b = k} B_sigma[a][b]
+// G_sigma[a][b], 16 complex numbers, and C_n = sum_k f_n(k) H_sigma(n)[k]
+// once per block.  Every colour sum of G lands in one H with a phase i^m
+// known at compile time: no per-bilinear folding per site.
+//
+// The source colour j of G's sum splits the work: wavefront j of a block
+// loads, for its 64 sites, the four S2 columns (beta, j) and the four S1
+// columns (beta', j) -- four when S1 and S2 are the same columns -- and forms
+// all 16 pairs (beta, beta'), sigma = beta ^ beta'.  Every column of a site
+// is read once per block, where the one-wavefront-per-sigma kernel reads it
+// four times (or eight, aliased).
+struct MesonFold {
+    int base[4][4][4];  // [sigma][a][b]: phase code of P_n0[a] Q_n0[b], n0 = members[sigma][0]
+    int sign[16][4];    // [n][k]: f_n(k)
+    int sigma_of[16];   // [n]: the coset of Gamma_n
+};
+constexpr MesonFold make_meson_fold() {
+    MesonFold F{};
+    const MesonTables T = make_meson_tables();
+    for (int sg = 0; sg < 4; ++sg) {
+        const int n0 = T.members[sg][0];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) F.base[sg][a][b] = (T.pcode[n0][a] + T.qcode[n0][b]) & 3;
+        for (int m = 0; m < 4; ++m) {
+            const int n = T.members[sg][m];
+            F.sigma_of[n] = sg;
+            for (int k = 0; k < 4; ++k) F.sign[n][k] = ((T.pcode[n][0] + T.qcode[n][k] - F.base[sg][0][k]) & 3) ? -1 : 1;
+        }
+    }
+    return F;
+}
+__device__ constexpr MesonFold kMesonFold = make_meson_fold();
+constexpr bool meson_fold_exact() {
+    const MesonTables T = make_meson_tables();
+    const MesonFold F = make_meson_fold();
+    for (int sg = 0; sg < 4; ++sg)
+        for (int m = 0; m < 4; ++m) {
+            const int n = T.members[sg][m];
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    const int d = (T.pcode[n][a] + T.qcode[n][b] - F.base[sg][a][b]) & 3;
+                    if (d != (F.sign[n][a ^ b] == 1 ? 0 : 2)) return false;
+                }
+        }
+    return true;
+}
+static_assert(meson_fold_exact(), "bilinears of a Klein coset differ by signs f_n(a ^ b)");
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// h += i^M sc (re + i im) with the phase folded into the signs
+template <int M>
+__device__ __forceinline__ void add_phased(double2& h, double sc, float re, float im) {
+    const double r = (double)re, i = (double)im;
+    if constexpr (M == 0) {
+        h.x = fmadd(sc, r, h.x);
+        h.y = fmadd(sc, i, h.y);
+    } else if constexpr (M == 1) {
+        h.x = fmadd(-sc, i, h.x);
+        h.y = fmadd(sc, r, h.y);
+    } else if constexpr (M == 2) {
+        h.x = fmadd(-sc, r, h.x);
+        h.y = fmadd(-sc, i, h.y);
+    } else {
+        h.x = fmadd(sc, i, h.x);
+        h.y = fmadd(-sc, r, h.y);
+    }
+}
+
+// The pair (S2 column (BETA, j), S1 column (BETA2, j)) of one site: for each
+// sink spin a, the colour sum of conj(S2[(a i),(BETA j)]) S1[(a ^ sigma, i),
+// (BETA2 j)] from the stored halves by v_dot2 (products exact, FP32 sums as
+// in the one-wavefront-per-sigma kernel), then both record scales in FP64.
+template <int BETA, int BETA2>
+__device__ __forceinline__ void meson_pair_f16s(const RawCol<QDP_F16S>& x, const RawCol<QDP_F16S>& y,
+                                                double2 (&H)[4][4]) {
+    constexpr int SIGMA = BETA ^ BETA2;
+    const double sc = (double)x.scale * (double)y.scale;
+    static_for<0, 4>([&](auto a_c) {
+        constexpr int a = decltype(a_c)::value;
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const half2_t xh = x.h[3 * a + c], yh = y.h[3 * (a ^ SIGMA) + c];
+            re = dot2_conj_re(xh, yh, re);
+            im = dot2_conj_im(xh, yh, im);
+        }
+        add_phased<kMesonFold.base[SIGMA][a][BETA]>(H[SIGMA][a ^ BETA], sc, re, im);
+    });
+}
+
+template <bool BUF, bool ALIAS>
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void meson_colour_kernel(ContractArgs A) {
+    const int t = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int j = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // source colour of this wavefront
+    const int lane = threadIdx.x & 63;
+    double2 H[4][4];
+#pragma unroll
+    for (int sg = 0; sg < 4; ++sg)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) H[sg][k] = make_double2(0.0, 0.0);
+    const int64_t Vsh = A.g.Vsh;
+    const int64_t Vs = 2 * Vsh;
+    for (int64_t l = (int64_t)chunk * 64 + lane; l < Vs; l += (int64_t)A.nchunks * 64) {
+        const int64_t p = l >= Vsh ? 1 : 0;
+        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
+        RawCol<QDP_F16S> x[4], y[ALIAS ? 1 : 4];
+#pragma unroll
+        for (int beta = 0; beta < 4; ++beta) {
+            load_column<QDP_F16S, BUF>(A.s2[3 * beta + j], s, x[beta]);
+            if constexpr (!ALIAS) load_column<QDP_F16S, BUF>(A.s1[3 * beta + j], s, y[beta]);
+        }
+        static_for<0, 4>([&](auto b_c) {
+            constexpr int BETA = decltype(b_c)::value;
+            static_for<0, 4>([&](auto b2_c) {
+                constexpr int BETA2 = decltype(b2_c)::value;
+                if constexpr (ALIAS)
+                    meson_pair_f16s<BETA, BETA2>(x[BETA], x[BETA2], H);
+                else
+                    meson_pair_f16s<BETA, BETA2>(x[BETA], y[BETA2], H);
+            });
+            // keep one S2 column's operands live at a time
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+    // block sum over the three colours (fixed order), then the bilinears
+    __shared__ double red[3][16][2];
+#pragma unroll
+    for (int sg = 0; sg < 4; ++sg)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double re = wave_sum(H[sg][k].x);
+            const double im = wave_sum(H[sg][k].y);
+            if (lane == 0) {
+                red[j][4 * sg + k][0] = re;
+                red[j][4 * sg + k][1] = im;
+            }
+        }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int n = threadIdx.x >> 1, ri = threadIdx.x & 1;
+        const int sg = kMesonFold.sigma_of[n];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double hk = (red[0][4 * sg + k][ri] + red[1][4 * sg + k][ri]) + red[2][4 * sg + k][ri];
+            v += kMesonFold.sign[n][k] * hk;
+        }
+        A.partial[(((int64_t)t * A.nchunks + chunk) * 16 + n) * 2 + ri] = v;
+    }
+}
+
 // out[((q * 16 + n) * Lt + (t - t0 mod Lt)) * 2 + k] = sum over chunks, fixed
 // order, for the nq momenta of a launch (nq = 1 at zero momentum).
 __global__ void meson_finish(const double* __restrict__ partial, int32_t Lt, int32_t nchunks, int32_t nq,
@@ -685,6 +852,15 @@ void* meson_func(int prec, bool buf, bool mom) {
     if (mom) return buf ? meson_func_buf<true, kMomPerLaunch>(prec) : meson_func_buf<false, kMomPerLaunch>(prec);
     return buf ? meson_func_buf<true, 0>(prec) : meson_func_buf<false, 0>(prec);
 }
+
+// The zero-momentum F16S contraction runs the one-wavefront-per-colour kernel.
+bool meson_by_colour(int prec, bool mom) { return prec == QDP_F16S && !mom; }
+void* meson_colour_func(bool buf, bool alias) {
+    if (buf) return alias ? reinterpret_cast<void*>(&meson_colour_kernel<true, true>)
+                          : reinterpret_cast<void*>(&meson_colour_kernel<true, false>);
+    return alias ? reinterpret_cast<void*>(&meson_colour_kernel<false, true>)
+                 : reinterpret_cast<void*>(&meson_colour_kernel<false, false>);
+}
 }  // namespace
 
 namespace {
@@ -748,8 +924,15 @@ qdp_status meson_launch(Ctx* ctx, ContractArgs& a, int32_t prec, bool mom, uint3
     const int32_t nq = mom ? kMomPerLaunch : 1;
     void* args[] = {&a};
     const bool buf = field_bytes(a.g, QDP_FERMION, prec) < (int64_t(1) << 32);
-    QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)a.nchunks, (unsigned)Lt), dim3(256),
-                                 args, 0, ctx->stream));
+    if (meson_by_colour(prec, mom)) {
+        bool alias = true;
+        for (int c = 0; c < 12; ++c) alias = alias && a.s1[c] == a.s2[c];
+        QDP_HIP(ctx, hipLaunchKernel(meson_colour_func(buf, alias), dim3((unsigned)a.nchunks, (unsigned)Lt),
+                                     dim3(192), args, 0, ctx->stream));
+    } else {
+        QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)a.nchunks, (unsigned)Lt),
+                                     dim3(256), args, 0, ctx->stream));
+    }
     QDP_CHECK(check_launch(ctx, "meson kernel"));
     const int nthreads = nq * 16 * Lt;
     hipLaunchKernelGGL(meson_finish, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,

@@ -238,3 +238,17 @@ def test_delta_pp_two_point(qdp, prec, dims):
     assert np.max(np.abs(np.roll(got, 1) - oracle.delta(Sr, dims, 1))) <= 1e-11 * np.max(np.abs(got))
     for f in u:
         qdp.free(f)
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16S"])
+def test_aliased_columns_match_copies_bitwise(qdp, prec):
+    """S1 and S2 naming the same columns (read once per site) gives the same
+    bits as S2 naming equal copies of them (both read)."""
+    dims = (6, 4, 4, 6)
+    S = synth.gaussian_propagator(dims, 203)
+    lat = qdp.lattice(dims)
+    a = upload_cols(qdp, lat, S, prec)
+    b = upload_cols(qdp, lat, [qdp.read(f) for f in a], prec)
+    assert np.array_equal(qdp.contract(a, a), qdp.contract(a, b))
+    for f in a + b:
+        qdp.free(f)
