@@ -703,8 +703,9 @@ def main():
                          "frac": MODEL_BYTES_PER_SITE_UPDATE[("F32", False)] * mean_units / (bl * 1e-3) / 1e9
                          / HBM_PEAK_GBPS},
             "launch_shape": batch["shape"],
-            "workload": "64 lattices from {8^3x16,12^3x24,16^3x32,24^3x48}, 12 columns, N 30, one persistent "
-                        "launch per iteration (median of 3 graph replays, HIP events) + 64 pion correlators"}
+            "workload": "64 lattices from {8^3x16,12^3x24,16^3x32,24^3x48}, 12 columns, N 30, one launch per "
+                        "iteration over all 64 lattices (median of 3 graph replays, HIP events) + 64 pion "
+                        "correlators"}
     if "c2" in res:
         c2 = res["c2"]
         out["c2_16c32_fp32"] = {"batched": {"value": c2["batched"]["value"], "ms": c2["batched"]["ms"]},

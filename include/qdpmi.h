@@ -489,10 +489,12 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
  * is 4 GiB or larger), zstack = 1 gives the site_waves wavefronts of a
  * block 64-site tiles one (x, y) plane apart (the tiles of z-neighbouring
  * sites, so that the neighbour records they share are read by one CU;
- * single-lattice launches with site_waves > 1, ignored otherwise) instead of
+ * single-lattice launches with site_waves > 1) instead of
  * consecutive tiles (zstack = 2: on whole-lattice updates with one column
  * group and an even site_waves, half of a block's waves take even tiles and
- * half the odd tiles with the same indices, z-stacked; elsewhere as 1),
+ * half the odd tiles with the same indices, z-stacked; elsewhere as 1; in
+ * qdp_smear_jacobi_batch, zstack = 1 launches one block per work item
+ * instead of the persistent grid that walks the item list),
  * lds = S (1 or 2; 0 = off) runs whole-lattice F16S
  * updates (QDP_SMEAR_FULL) with the kernel that stages each block's x/y
  * neighbour window in LDS, blocks of 2 S wavefronts updating 64 S

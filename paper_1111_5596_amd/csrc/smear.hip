@@ -50,6 +50,7 @@ struct SmearLaunch {
     int32_t interleave;  // whole lattice: block 2b = even tile b, 2b+1 = odd tile b
     int32_t zstride;     // > 0: the waves of a block take 64-site tiles zstride apart
     int32_t xcd_group;   // xcd = 2: logical blocks per group kept on one XCD
+    int32_t one_item;    // multi-lattice kernel: block b takes work item b only
     double kappa;
 };
 
@@ -612,23 +613,33 @@ __global__ __launch_bounds__(128 * S) __attribute__((amdgpu_waves_per_eu(2))) vo
     }
 }
 
-// Persistent multi-lattice kernel: a grid of as many blocks as the chip
-// holds at once walks a work list of (lattice, tile) items, block b taking
-// items b, b + grid, b + 2 grid, ...  At every step the blocks in flight
+// Multi-lattice kernel over a work list of (lattice, tile) items, ordered by
+// lattice; a lattice's items alternate between its even and its odd tiles
+// (even tile k and odd tile k hold each other's neighbours).  Persistent
+// form: a grid of as many blocks as the chip holds at once, block b taking
+// items b, b + grid, b + 2 grid, ...; at every step the blocks in flight
 // work on one contiguous run of items (one XCD's blocks on one sub-run when
 // the mapping is XCD-aware), so neighbouring tiles are read while in L2, as
-// in a one-lattice launch.  A lattice's items alternate between its even
-// and its odd tiles: even tile k and odd tile k hold each other's
-// neighbours.
+// in a one-lattice launch.  One-item form (ln.one_item): a block per item,
+// the hardware dispatching them in order, so the blocks in flight never
+// drift apart over the list.
 template <int PREC, int OCC, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1))) void smear_batch_kernel(
     const SmearJob* __restrict__ jobs, const int64_t* __restrict__ tile_start, int32_t njobs, SmearLaunch ln) {
     const int64_t ntiles = tile_start[njobs];
     int64_t b = blockIdx.x;
     if (ln.xcd) b = xcd_logical_block(b, gridDim.x);
+    const int64_t stride = ln.one_item ? ntiles : (int64_t)gridDim.x;
     int j = 0;
-    for (int64_t t = b; t < ntiles; t += gridDim.x) {
-        while (j + 1 < njobs && tile_start[j + 1] <= t) ++j;  // items are ordered by lattice
+    for (int64_t t = b; t < ntiles; t += stride) {
+        // the item's lattice: the last j with tile_start[j] <= t
+        int lo = j, hi = njobs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tile_start[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        j = lo;
         const SmearJob& job = jobs[j];
         const int64_t u = t - tile_start[j];
         tile_update<PREC, BUF>(job, u >> 1, (u & 1) * job.g.Vh, job.g.Vh, ln.site_waves, ln.col_groups, 0,
@@ -1199,15 +1210,17 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
         ln.xcd = sh.xcd;
         ln.kappa = kappa;
         const int64_t ntiles = h_tiles[k * (njobs + 1) + njobs];
+        ln.one_item = sh.zstack == 1 ? 1 : 0;
         Launch L;
         L.func = smear_func(prec, sh, true);
         L.block = dim3((unsigned)(64 * sh.site_waves * sh.col_groups));
-        // as many blocks as are resident at once (a multiple of 8 for the XCD mapping)
+        // persistent: as many blocks as are resident at once; one item per
+        // block: every item (a multiple of 8 for the XCD mapping either way)
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, L.func, (int)L.block.x, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        int64_t grid = std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * per_cu);
+        int64_t grid = ln.one_item ? ntiles : std::min<int64_t>(ntiles, (int64_t)ctx->num_cus * per_cu);
         grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
         const int64_t* T = reinterpret_cast<const int64_t*>(d_tiles) + k * (njobs + 1);
         L.grid = dim3((unsigned)grid);
@@ -1233,12 +1246,13 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
             QDP_HIP(ctx, hipEventCreate(&e0));
             QDP_HIP(ctx, hipEventCreate(&e1));
             const int groups[] = {1, 2, 3, 4, 6};
+            for (int one : {0, 1})
             for (int sw : {1, 2, 4})
                 for (int cg : groups)
                     for (int xcd : {0, 1})
                         for (int occ : {0, 2, 3}) {
                             if (sw * cg > 4 || (prec == QDP_F64 && occ)) continue;
-                            const qdp_launch_shape cand{sw, cg, xcd, occ, flat, 0, 0};
+                            const qdp_launch_shape cand{sw, cg, xcd, occ, flat, one, 0};
                             Launch L = batch_launch(d_first, cand);
                             auto p = arg_pointers(L);
                             float best = 1e30f;
@@ -1257,8 +1271,8 @@ qdp_status smear_batch_impl(Ctx* ctx, const qdp_smear_job* jobs, int32_t njobs, 
                                 if (rep > 0) best = std::min(best, t);
                             }
                             if (log)
-                                std::fprintf(stderr, "[qdpmi autotune] batch of %d prec %d shape %d %d %d %d %d: %.4f ms\n",
-                                             njobs, prec, sw, cg, xcd, occ, flat, best);
+                                std::fprintf(stderr, "[qdpmi autotune] batch of %d prec %d shape %d %d %d %d %d %d: %.4f ms\n",
+                                             njobs, prec, sw, cg, xcd, occ, flat, one, best);
                             if (best < best_ms * kTuneMargin) {
                                 best_ms = best;
                                 sh = cand;

@@ -283,14 +283,16 @@ def _device_equal(q, a, b):
     return d[0, 0].real == 0.0
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1, 2, 0, 0), (2, 2, 0, 0, 0, 0), None])
+@pytest.mark.parametrize("shape", [(1, 1, 1, 2, 0, 0), (2, 2, 0, 0, 0, 0), (1, 1, 1, 2, 0, 1), (2, 2, 0, 0, 0, 1),
+                                   None])
 def test_batch_blocks_walk_across_lattices_bitwise(qdp, shape):
     """More work items than the persistent grid has blocks: the lattices hold
     over 10k (lattice, 64-site tile) items, above the most 64-thread blocks
     256 CUs can hold (32 waves each), so blocks take several items, and their
-    later items lie in other lattices.  Every column of every lattice must
-    equal the one-lattice smearing bitwise; two columns of the small lattices
-    are also checked against the oracle."""
+    later items lie in other lattices (zstack = 1: one block per item, the
+    lattice found by a search over the item offsets).  Every column of every
+    lattice must equal the one-lattice smearing bitwise; two columns of the
+    small lattices are also checked against the oracle."""
     sizes = [(16, 16, 16, 32), (6, 6, 6, 4), (16, 16, 16, 32), (12, 12, 12, 24), (16, 16, 16, 32),
              (8, 8, 8, 16), (16, 16, 16, 32), (16, 16, 16, 32), (4, 4, 4, 8)]
     items = sum(2 * -(-synth.volume(d) // 2 // 64) for d in sizes)
