@@ -51,6 +51,8 @@ struct SmearLaunch {
     int32_t zstride;     // > 0: the waves of a block take 64-site tiles zstride apart
     int32_t xcd_group;   // xcd = 2: logical blocks per group kept on one XCD
     int32_t one_item;    // multi-lattice kernel: block b takes work item b only
+    int32_t bands;       // LDS-window kernel: y bands walked one after another (1 = none)
+    int32_t pad2;
     double kappa;
 };
 
@@ -433,6 +435,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? OCC :
 // current column's z terms are done.  Same per-site arithmetic and hop order
 // as every other variant, so the same bits.
 //
+// Block order: block b takes i0 = 64 S b, or, with y bands (ln.bands > 1),
+// the lattice's (x, y) planes of a parity are cut into bands of Ly / bands
+// rows and the blocks walk band 0 of every plane, then band 1, ...; with the
+// XCD-aware mapping each XCD then walks one band over its share of the
+// planes, so the z neighbours it reads lie one band-plane, not one plane,
+// behind or ahead of the sites it updates, and stay in its L2 until reused.
+//
 // LDS buffer layout: rows of Wp = 64 (S + 1) slots, window site w of parity
 // p in slot w (the slots past the window hold copies of its last site and
 // are never read): chunk row r at ((p * 3 + r) * Wp + w) * 16, then the scale
@@ -468,7 +477,14 @@ __global__ __launch_bounds__(128 * S) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int32_t Vh = (int32_t)g.Vh;
     const int32_t q = wave >= S ? 1 : 0;  // parity of this wave's sites
-    const int32_t i0 = (int32_t)b * 64 * S;
+    int32_t i0 = (int32_t)b * 64 * S;
+    if (ln.bands > 1) {
+        // blocks per band of one plane, then (band, plane, block in band)
+        const int32_t plane = g.Lxh * g.L[1], band_sites = plane / ln.bands, per_band = band_sites / (64 * S);
+        const int32_t planes = Vh / plane;
+        const int32_t bnd = (int32_t)b / (planes * per_band), r = (int32_t)b - bnd * planes * per_band;
+        i0 = (r / per_band) * plane + bnd * band_sites + (r % per_band) * 64 * S;
+    }
     const int32_t i = i0 + 64 * (wave - q * S) + lane;
     const bool active = i < Vh;
     const int32_t s = q * Vh + (active ? i : Vh - 1);  // a valid site for the inactive lanes' addresses
@@ -784,6 +800,16 @@ bool lds_eligible(int prec, const SmearJob& job, int64_t begin, int64_t count, c
     return job.g.Lxh <= kLdsMaxHalfX;
 }
 
+// y bands of the LDS-window kernel for zstack = 1 (two) or 2 (four), when
+// Ly splits evenly and a band of one plane is a whole number of blocks;
+// else 1 (plain order).
+int32_t lds_bands(const SmearJob& job, const qdp_launch_shape& sh) {
+    const int32_t bands = sh.zstack == 1 ? 2 : (sh.zstack == 2 ? 4 : 1);
+    if (bands == 1 || job.g.L[1] % bands) return 1;
+    const int64_t band_sites = (int64_t)job.g.Lxh * job.g.L[1] / bands;
+    return band_sites % (64LL * sh.lds) == 0 ? bands : 1;
+}
+
 // A pass over [begin, begin + count); count == V (the whole lattice) runs
 // the two parities' tiles interleaved.
 Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t count,
@@ -795,6 +821,7 @@ Launch make_single_launch(int prec, const SmearJob& job, int64_t begin, int64_t 
         ln.interleave = 1;
         ln.xcd = sh.xcd ? 1 : 0;
         ln.kappa = kappa;
+        ln.bands = lds_bands(job, sh);
         ln.nlogical = (job.g.Vh + 64LL * sh.lds - 1) / (64LL * sh.lds);
         const int64_t grid = ln.xcd ? (ln.nlogical + 7) / 8 * 8 : ln.nlogical;
         Launch L;
@@ -954,10 +981,12 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
                         }
             }
         for (int S : {1, 2})
-            for (int xcd : {0, 1}) {
-                const qdp_launch_shape sh{1, 1, xcd, 0, flat, 0, S};
-                if (lds_eligible(prec, job, begin, count, sh)) cands.push_back(sh);
-            }
+            for (int xcd : {0, 1})
+                for (int zs : {0, 1, 2}) {
+                    const qdp_launch_shape sh{1, 1, xcd, 0, flat, zs, S};
+                    if (lds_eligible(prec, job, begin, count, sh) && (zs == 0 || lds_bands(job, sh) > 1))
+                        cands.push_back(sh);
+                }
         // two rounds over the candidates, each keeping its faster time, so
         // that no candidate's figure depends on where in the sequence the
         // clocks or caches happened to be

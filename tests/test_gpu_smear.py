@@ -140,16 +140,19 @@ def test_launch_shapes_bitwise(qdp, prec):
 
 
 @pytest.mark.parametrize("dims", [(8, 8, 4, 4), (12, 12, 12, 4), (20, 20, 4, 2), (24, 12, 4, 2), (6, 6, 2, 2),
-                                  (48, 48, 8, 4), (16, 2, 4, 2)])
+                                  (48, 48, 8, 4), (16, 2, 4, 2), (16, 32, 4, 2)])
 @pytest.mark.parametrize("source", ["gaussian", "point"])
 def test_lds_window_kernel_bitwise(qdp, dims, source):
     """The whole-lattice F16S kernel that stages the x/y neighbour window in
     LDS (blocks of 2 S waves over 64 S indices of both parities), S = 1, 2,
-    both block mappings, against the kernels without LDS in both modes:
-    windows that cover the whole parity range, a block range past the end of
-    a parity (12^3 x 4: 3456 indices per parity), y hops that wrap out of the
-    window (20^2 and 48^2 planes) and Ly = 2; point sources (all-zero records
-    beside non-zero ones) and Gaussian columns."""
+    both block mappings, plain order and two or four y bands (zstack 1, 2;
+    bands apply where a band of a plane is whole blocks: 48^2 planes with
+    S = 1 and two bands, 16 x 32 planes with every S and band count),
+    against the kernels without LDS in both modes: windows that cover the
+    whole parity range, a block range past the end of a parity (12^3 x 4:
+    3456 indices per parity), y hops that wrap out of the window (20^2 and
+    48^2 planes) and Ly = 2; point sources (all-zero records beside non-zero
+    ones) and Gaussian columns."""
     U = synth.su3_links(dims, 17)
     if source == "point":
         psi = synth.point_source(dims, range(12), site=synth.volume(dims) // 3)
@@ -159,7 +162,9 @@ def test_lds_window_kernel_bitwise(qdp, dims, source):
     try:
         ref = None
         for shape, mode in [((1, 1, 0, 0, 0, 0, 0), 1), ((4, 1, 1, 2, 0, 1, 0), 0), ((1, 1, 0, 0, 0, 0, 1), 0),
-                            ((1, 1, 1, 0, 0, 0, 1), 0), ((1, 1, 0, 0, 0, 0, 2), 0), ((1, 1, 1, 0, 0, 0, 2), 0)]:
+                            ((1, 1, 1, 0, 0, 0, 1), 0), ((1, 1, 0, 0, 0, 0, 2), 0), ((1, 1, 1, 0, 0, 0, 2), 0),
+                            ((1, 1, 1, 0, 0, 1, 1), 0), ((1, 1, 0, 0, 0, 1, 1), 0), ((1, 1, 1, 0, 0, 2, 1), 0),
+                            ((1, 1, 1, 0, 0, 1, 2), 0), ((1, 1, 1, 0, 0, 2, 2), 0)]:
             qdp.set_shape(*shape)
             outs = [qdp.alloc(lat, "FERMION", "F16S") for _ in fs]
             qdp.smear_to(g, fs, outs, 0.25, 6, mode=mode)
