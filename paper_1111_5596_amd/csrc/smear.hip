@@ -516,22 +516,33 @@ __global__ __launch_bounds__(128 * S) __attribute__((amdgpu_waves_per_eu(2))) vo
     // copy the window of column c into an LDS buffer: the eight (parity p,
     // row r; r = 3 the scales) rows dealt to the waves in turn, S + 1 full
     // 64-lane pieces each (no lane divergence: lanes past the window copy
-    // its last site into padding slots)
+    // its last site into padding slots).  The byte offsets of a wave's
+    // pieces are the same for every column: computed once.
+    constexpr int kRows = 8 / (2 * S);  // rows per wave
+    int32_t stage_off[kRows][S + 1];
+#pragma unroll
+    for (int jj = 0; jj < kRows; ++jj) {
+        const int j = wave + 2 * S * jj, p = j >> 2, r = j & 3;
+#pragma unroll
+        for (int k = 0; k <= S; ++k) {
+            const int32_t site = p * Vh + wbeg + min(64 * k + lane, wlen - 1);
+            stage_off[jj][k] = (int32_t)(r < 3 ? tile_site_offset(tbc, 16, site) : site_off<float>(site, tbc));
+        }
+    }
     auto stage = [&](int c, char* base) {
         const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(job.src[c]);
-        for (int j = wave; j < 8; j += 2 * S) {
-            const int p = j >> 2, r = j & 3;
+#pragma unroll
+        for (int jj = 0; jj < kRows; ++jj) {
+            const int j = wave + 2 * S * jj, p = j >> 2, r = j & 3;
 #pragma unroll
             for (int k = 0; k <= S; ++k) {
-                const int32_t site = p * Vh + wbeg + min(64 * k + lane, wlen - 1);
+                const int vo = stage_off[jj][k];
                 if (r < 3)
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        rs, (lds_void_t*)(base + ((p * 3 + r) * Wp + 64 * k) * 16), 16,
-                        (int)(uint32_t)tile_site_offset(tbc, 16, site), r * 1024, 0, 0);
+                        rs, (lds_void_t*)(base + ((p * 3 + r) * Wp + 64 * k) * 16), 16, vo, r * 1024, 0, 0);
                 else
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        rs, (lds_void_t*)(base + 96 * Wp + (p * Wp + 64 * k) * 4), 4,
-                        (int)(uint32_t)site_off<float>(site, tbc), 12 * 256, 0, 0);
+                        rs, (lds_void_t*)(base + 96 * Wp + (p * Wp + 64 * k) * 4), 4, vo, 12 * 256, 0, 0);
             }
         }
     };
