@@ -10,12 +10,13 @@
 //   G_sigma[a][b] = sum_{i,j colour} conj(S2[(a i),(b j)]) S1[(sigma a, i),(sigma b, j)]
 //
 // and C_n = sum_{a,b} P_n[a] Q_n[b] G_sigma[a][b] with P_n[a] = s_a Gamma_n[a, sigma a],
-// Q_n[b] = s_b Gamma_n[sigma b, b], s = diag(g5).  Zero-momentum F16S
-// contractions run one wavefront per source colour (each column of a site
-// read once per block); the other precisions and the momentum-projected
-// contractions run one wavefront per sigma, the four wavefronts of a block
-// reading the same 64 sites.  Momentum projection weights each site's traces
-// by exp(-i p.x) before the slice sum; one launch carries up to four momenta.
+// Q_n[b] = s_b Gamma_n[sigma b, b], s = diag(g5).  F16S contractions run one
+// wavefront per source colour (each column of a site read once per block;
+// with momenta when S1 and S2 are the same columns); the other precisions
+// and the momentum-projected contractions of two propagators run one
+// wavefront per sigma, the four wavefronts of a block reading the same 64
+// sites.  Momentum projection weights each site's traces by exp(-i p.x)
+// before the slice sum; one launch carries up to four momenta.
 // Products and sums are FP64 (propagators grow like 2^N under smearing and
 // |S|^2 leaves the FP32 range).  The time-slice sums are two-stage with a
 // fixed order: bitwise repeatable.
@@ -466,6 +467,29 @@ __device__ __forceinline__ void meson_pair_f16s(const RawCol<QDP_F16S>& x, const
     });
 }
 
+// H += the 16 pairs of source colour j at site s
+template <bool BUF, bool ALIAS>
+__device__ __forceinline__ void colour_site_sums(const ContractArgs& A, int32_t s, int j, double2 (&H)[4][4]) {
+    RawCol<QDP_F16S> x[4], y[ALIAS ? 1 : 4];
+#pragma unroll
+    for (int beta = 0; beta < 4; ++beta) {
+        load_column<QDP_F16S, BUF>(A.s2[3 * beta + j], s, x[beta]);
+        if constexpr (!ALIAS) load_column<QDP_F16S, BUF>(A.s1[3 * beta + j], s, y[beta]);
+    }
+    static_for<0, 4>([&](auto b_c) {
+        constexpr int BETA = decltype(b_c)::value;
+        static_for<0, 4>([&](auto b2_c) {
+            constexpr int BETA2 = decltype(b2_c)::value;
+            if constexpr (ALIAS)
+                meson_pair_f16s<BETA, BETA2>(x[BETA], x[BETA2], H);
+            else
+                meson_pair_f16s<BETA, BETA2>(x[BETA], y[BETA2], H);
+        });
+        // keep one S2 column's operands live at a time
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
 template <bool BUF, bool ALIAS>
 __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void meson_colour_kernel(ContractArgs A) {
     const int t = blockIdx.y;
@@ -482,24 +506,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void m
     for (int64_t l = (int64_t)chunk * 64 + lane; l < Vs; l += (int64_t)A.nchunks * 64) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
-        RawCol<QDP_F16S> x[4], y[ALIAS ? 1 : 4];
-#pragma unroll
-        for (int beta = 0; beta < 4; ++beta) {
-            load_column<QDP_F16S, BUF>(A.s2[3 * beta + j], s, x[beta]);
-            if constexpr (!ALIAS) load_column<QDP_F16S, BUF>(A.s1[3 * beta + j], s, y[beta]);
-        }
-        static_for<0, 4>([&](auto b_c) {
-            constexpr int BETA = decltype(b_c)::value;
-            static_for<0, 4>([&](auto b2_c) {
-                constexpr int BETA2 = decltype(b2_c)::value;
-                if constexpr (ALIAS)
-                    meson_pair_f16s<BETA, BETA2>(x[BETA], x[BETA2], H);
-                else
-                    meson_pair_f16s<BETA, BETA2>(x[BETA], y[BETA2], H);
-            });
-            // keep one S2 column's operands live at a time
-            __builtin_amdgcn_sched_barrier(0);
-        });
+        colour_site_sums<BUF, ALIAS>(A, s, j, H);
     }
     // block sum over the three colours (fixed order), then the bilinears
     __shared__ double red[3][16][2];
@@ -525,6 +532,76 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void m
             v += kMesonFold.sign[n][k] * hk;
         }
         A.partial[(((int64_t)t * A.nchunks + chunk) * 16 + n) * 2 + ri] = v;
+    }
+}
+
+// Momentum-projected F16S contraction, four momenta per launch.  Waves 0..2
+// form a site's 16 sums H_sigma[k] for their source colour as above; the
+// three colours' sums meet in LDS, and wavefront q (0..3) adds them (fixed
+// order) and weights them by the plane wave of momentum q at the site, so
+// each site's phase is computed once per momentum.  C_n = sum_k f_n(k)
+// H_sigma(n)[k] once per block, as at zero momentum.
+constexpr int kColourMomenta = 4;
+template <bool BUF, bool ALIAS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void meson_colour_mom_kernel(ContractArgs A) {
+    const int t = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // colour (w < 3) and momentum
+    const int lane = threadIdx.x & 63;
+    __shared__ double2 hs[3][16][64];
+    double2 C[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) C[e] = make_double2(0.0, 0.0);
+    const int64_t Vsh = A.g.Vsh;
+    const int64_t Vs = 2 * Vsh;
+    // every wavefront walks the same sites: the trip count is uniform over
+    // the block (barriers inside); lanes past the slice take zeros
+    for (int64_t base = (int64_t)chunk * 64; base < Vs; base += (int64_t)A.nchunks * 64) {
+        const int64_t l = base + lane;
+        const bool active = l < Vs;
+        const int64_t lc = active ? l : Vs - 1;
+        const int64_t p = lc >= Vsh ? 1 : 0;
+        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (lc - p * Vsh));
+        if (w < 3) {
+            double2 H[4][4];
+#pragma unroll
+            for (int sg = 0; sg < 4; ++sg)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) H[sg][k] = make_double2(0.0, 0.0);
+            colour_site_sums<BUF, ALIAS>(A, s, w, H);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) hs[w][e][lane] = active ? H[e >> 2][e & 3] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        int32_t c[4];
+        cb_coords(A.g, s, c);
+        const double2 ph = plane_wave(A.g, A.mom[w], c);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const double2 a = hs[0][e][lane], b = hs[1][e][lane], d = hs[2][e][lane];
+            const double2 h = make_double2((a.x + b.x) + d.x, (a.y + b.y) + d.y);
+            cmac(C[e], ph, h);
+        }
+        __syncthreads();
+    }
+    __shared__ double red[kColourMomenta][16][2];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const double re = wave_sum(C[e].x);
+        const double im = wave_sum(C[e].y);
+        if (lane == 0) {
+            red[w][e][0] = re;
+            red[w][e][1] = im;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * 16 * kColourMomenta) {
+        const int q = threadIdx.x >> 5, n = (threadIdx.x >> 1) & 15, ri = threadIdx.x & 1;
+        const int sg = kMesonFold.sigma_of[n];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += kMesonFold.sign[n][k] * red[q][4 * sg + k][ri];
+        A.partial[((((int64_t)t * A.nchunks + chunk) * kColourMomenta + q) * 16 + n) * 2 + ri] = v;
     }
 }
 
@@ -853,9 +930,14 @@ void* meson_func(int prec, bool buf, bool mom) {
     return buf ? meson_func_buf<true, 0>(prec) : meson_func_buf<false, 0>(prec);
 }
 
-// The zero-momentum F16S contraction runs the one-wavefront-per-colour kernel.
-bool meson_by_colour(int prec, bool mom) { return prec == QDP_F16S && !mom; }
-void* meson_colour_func(bool buf, bool alias) {
+// F16S contractions run the one-wavefront-per-colour kernels (with momenta:
+// when S1 and S2 are the same columns; two propagators' registers and the
+// momentum sums do not fit one wavefront's registers)
+bool meson_by_colour(int prec, bool mom, bool alias) { return prec == QDP_F16S && (!mom || alias); }
+static_assert(kColourMomenta == kMomPerLaunch, "one wavefront per momentum of a launch");
+void* meson_colour_func(bool buf, bool alias, bool mom) {
+    if (mom) return buf ? reinterpret_cast<void*>(&meson_colour_mom_kernel<true, true>)
+                        : reinterpret_cast<void*>(&meson_colour_mom_kernel<false, true>);
     if (buf) return alias ? reinterpret_cast<void*>(&meson_colour_kernel<true, true>)
                           : reinterpret_cast<void*>(&meson_colour_kernel<true, false>);
     return alias ? reinterpret_cast<void*>(&meson_colour_kernel<false, true>)
@@ -924,11 +1006,11 @@ qdp_status meson_launch(Ctx* ctx, ContractArgs& a, int32_t prec, bool mom, uint3
     const int32_t nq = mom ? kMomPerLaunch : 1;
     void* args[] = {&a};
     const bool buf = field_bytes(a.g, QDP_FERMION, prec) < (int64_t(1) << 32);
-    if (meson_by_colour(prec, mom)) {
-        bool alias = true;
-        for (int c = 0; c < 12; ++c) alias = alias && a.s1[c] == a.s2[c];
-        QDP_HIP(ctx, hipLaunchKernel(meson_colour_func(buf, alias), dim3((unsigned)a.nchunks, (unsigned)Lt),
-                                     dim3(192), args, 0, ctx->stream));
+    bool alias = true;
+    for (int c = 0; c < 12; ++c) alias = alias && a.s1[c] == a.s2[c];
+    if (meson_by_colour(prec, mom, alias)) {
+        QDP_HIP(ctx, hipLaunchKernel(meson_colour_func(buf, alias, mom), dim3((unsigned)a.nchunks, (unsigned)Lt),
+                                     dim3(mom ? 256 : 192), args, 0, ctx->stream));
     } else {
         QDP_HIP(ctx, hipLaunchKernel(meson_func(prec, buf, mom), dim3((unsigned)a.nchunks, (unsigned)Lt),
                                      dim3(256), args, 0, ctx->stream));

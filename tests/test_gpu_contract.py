@@ -160,6 +160,12 @@ def test_meson_momentum_projection(qdp, prec, dims):
     # p = 0 agrees with the zero-momentum call
     c0 = qdp.contract(a, b)
     assert np.max(np.abs(got[0] - c0)) <= 1e-13 * np.max(np.abs(c0))
+    # S1 and S2 the same columns (F16S: the one-wavefront-per-colour kernel)
+    ref11 = oracle.meson_mom(S1r, S1r, dims, MOMS)
+    got11 = qdp.contract_mom(a, a, MOMS)
+    assert np.max(np.abs(got11 - ref11)) <= tol * np.max(np.abs(ref11))
+    c11 = qdp.contract(a, a)
+    assert np.max(np.abs(got11[0] - c11)) <= 1e-13 * np.max(np.abs(c11))
     # mask and time origin
     part = qdp.contract_mom(a, b, MOMS[1:3], mask=1 << 15, t0=2)
     assert np.count_nonzero(part[:, :15]) == 0
