@@ -811,14 +811,19 @@ bool lds_eligible(int prec, const SmearJob& job, int64_t begin, int64_t count, c
     return job.g.Lxh <= kLdsMaxHalfX;
 }
 
-// y bands of the LDS-window kernel for zstack = 1 (two) or 2 (four), when
-// Ly splits evenly and a band of one plane is a whole number of blocks;
-// else 1 (plain order).
+// y bands of the LDS-window kernel for zstack = 1 (two, or three when two
+// do not fit) or 2 (four), when Ly splits evenly and a band of one plane is
+// a whole number of blocks; else 1 (plain order).
 int32_t lds_bands(const SmearJob& job, const qdp_launch_shape& sh) {
-    const int32_t bands = sh.zstack == 1 ? 2 : (sh.zstack == 2 ? 4 : 1);
-    if (bands == 1 || job.g.L[1] % bands) return 1;
-    const int64_t band_sites = (int64_t)job.g.Lxh * job.g.L[1] / bands;
-    return band_sites % (64LL * sh.lds) == 0 ? bands : 1;
+    auto fits = [&](int32_t bands) {
+        return job.g.L[1] % bands == 0 && ((int64_t)job.g.Lxh * job.g.L[1] / bands) % (64LL * sh.lds) == 0;
+    };
+    if (sh.zstack == 1) {  // the fewest bands that fit: 2, else 3
+        if (fits(2)) return 2;
+        if (fits(3)) return 3;
+    }
+    if (sh.zstack == 2 && fits(4)) return 4;
+    return 1;
 }
 
 // A pass over [begin, begin + count); count == V (the whole lattice) runs

@@ -145,9 +145,10 @@ def test_launch_shapes_bitwise(qdp, prec):
 def test_lds_window_kernel_bitwise(qdp, dims, source):
     """The whole-lattice F16S kernel that stages the x/y neighbour window in
     LDS (blocks of 2 S waves over 64 S indices of both parities), S = 1, 2,
-    both block mappings, plain order and two or four y bands (zstack 1, 2;
-    bands apply where a band of a plane is whole blocks: 48^2 planes with
-    S = 1 and two bands, 16 x 32 planes with every S and band count),
+    both block mappings, plain order and two, three or four y bands
+    (zstack 1, 2; bands apply where a band of a plane is whole blocks: 48^2
+    planes with two bands for S = 1 and three for S = 2, 16 x 32 planes with
+    every S and band count),
     against the kernels without LDS in both modes: windows that cover the
     whole parity range, a block range past the end of a parity (12^3 x 4:
     3456 indices per parity), y hops that wrap out of the window (20^2 and
