@@ -996,9 +996,12 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
                             cands.push_back(qdp_launch_shape{sw, cg, xcd, occ, flat, zs, 0});
                         }
             }
+        // the banded orders first: they fetch fewer bytes, so on a tie
+        // within the timing margin the one that loads the memory system
+        // less is kept
         for (int S : {1, 2})
             for (int xcd : {0, 1})
-                for (int zs : {0, 1, 2}) {
+                for (int zs : {1, 2, 0}) {
                     const qdp_launch_shape sh{1, 1, xcd, 0, flat, zs, S};
                     if (lds_eligible(prec, job, begin, count, sh) && (zs == 0 || lds_bands(job, sh) > 1))
                         cands.push_back(sh);
