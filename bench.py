@@ -431,6 +431,13 @@ def measured_traffic(shape=None, mode="full"):
     return None
 
 
+def smear_kernel_name(shape):
+    """The smearing kernel a launch shape (site_waves, col_groups, xcd,
+    waves_per_simd, flat, zstack, lds) runs on a whole F16S lattice."""
+    lds = int(shape[6]) if len(shape) > 6 else 0
+    return f"smear_lds_kernel<{lds}>" if lds else "smear_kernel"
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -657,7 +664,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "smear_kernel<F16S> (both checkerboard subsets in one launch, 12 columns)",
+                     "kernel": smear_kernel_name(f16["shape"]) + " (F16S, both checkerboard subsets in one launch, "
+                               "12 columns)",
                      "bytes_per_launch": model_bytes, "units_per_launch": per_launch_units,
                      "bytes_per_unit": bpu, "launch_ms": launch_ms},
         "smear_ms_per_step": f16["smear_ms"],
