@@ -495,15 +495,15 @@ qdp_status qdp_fill_point(qdp_ctx* ctx, qdp_field f, int64_t site, int32_t spin,
  * half the odd tiles with the same indices, z-stacked; elsewhere as 1; in
  * qdp_smear_jacobi_batch, zstack = 1 launches one block per work item
  * instead of the persistent grid that walks the item list),
- * lds = S (1 or 2; 0 = off) runs whole-lattice F16S
- * updates (QDP_SMEAR_FULL) with the kernel that stages each block's x/y
- * neighbour window in LDS, blocks of 2 S wavefronts updating 64 S
- * checkerboard indices of both parities (site_waves, col_groups and
- * waves_per_simd do not apply to it; zstack = 1 or 2 orders its blocks by
- * two (three where two do not fit) or four y bands of the (x, y) planes, one
- * band over all planes after the other, where Ly splits evenly and a band of
- * a plane is a whole number of blocks, else the plain order; other launches, or lattices whose window
- * does not fit in 64 KB of LDS, ignore lds).
+ * lds = S (1 or 2; 0 = off) runs whole-lattice F16S updates
+ * (QDP_SMEAR_FULL) with the kernel that stages each block's x/y neighbour
+ * window in LDS, blocks of 2 S wavefronts updating 64 S checkerboard
+ * indices of both parities (site_waves, col_groups and waves_per_simd do
+ * not apply to it; zstack = 1 or 2 orders its blocks by two (three where two
+ * do not fit) or four y bands of the (x, y) planes, one band over all planes
+ * after the other, where Ly splits evenly and a band of a plane is a whole
+ * number of blocks, else the plain order; other launches, flat addressing
+ * and lattices with Lx > 64 ignore lds).
  * Every shape computes bitwise-identical results.
  * qdp_smear_set_shape forces a shape (site_waves = 0 returns to
  * autotuning); qdp_smear_get_shape reports the shape the last smearing call
