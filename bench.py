@@ -285,8 +285,8 @@ def run_config3(q, torch):
 
 def run_batch64(q, torch, reps=3):
     """The multi-lattice workload: 64 lattices drawn from 8^3x16 .. 24^3x48,
-    12-column point sources, kappa 0.25, N 30, FP32, one persistent launch
-    per iteration replayed from a HIP graph; then the pion correlator of each
+    12-column point sources, kappa 0.25, N 30, FP32, one launch over all the
+    lattices per iteration replayed from a HIP graph; then the pion correlator of each
     lattice.  The smearing is timed with HIP events on the library's stream
     (median of `reps` replays), the 64 contractions separately."""
     from paper_1111_5596_amd import synth
