@@ -613,8 +613,11 @@ __global__ __launch_bounds__(128 * S) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int k = 0; k < 12; ++k) v[k] = xh == 3 ? xv[k] : v[k];
         }
         hop_accumulate_f16s<3>(acc, L, H, v);
-        // the next column's z (and wrapped y) records: the registers are free now
-        if (c + 1 < c1) load_z(c + 1);
+        // the next column's z (and wrapped y) records: the registers are free
+        // now.  Requested on every column (the last one fetches its own again):
+        // a conditional load would make the compiler copy these registers
+        // around the branch on every column.
+        load_z(min(c + 1, c1 - 1));
         lds_record(rd, 1 - q, slot[4], v);
         hop_accumulate_f16s<4>(acc, L, H, v);
         lds_record(rd, 1 - q, slot[5], v);
