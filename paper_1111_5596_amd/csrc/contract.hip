@@ -713,28 +713,41 @@ __device__ __forceinline__ double2 inner_plain(const double2 A[4][4], const doub
 }
 
 // <X P Y, M> = sum_{r, g} (X P)_{rg} (Y M^T)_{gr}.
+// Tr(X P Y M^T) with the rank-2 projector P = (1 + 2 hp gamma_4) / 2 =
+// (1/2) sum_k u_k u_k^T, u_k = e_k + s e_{k+2} (s = 2 hp = +1 or -1; gamma_4
+// swaps spins 0 <-> 2 and 1 <-> 3 with unit entries): (1/2) sum_k
+// (Y^T u_k) . M^T (X u_k), 2 x 20 complex MACs instead of 80.
+constexpr bool gamma4_swaps_pairs() {
+    for (int g = 0; g < 4; ++g)
+        if (kGamma4.perm[g] != (g ^ 2) || kGamma4.code[g] != 0) return false;
+    return true;
+}
+static_assert(gamma4_swaps_pairs(), "DeGrand-Rossi gamma_4 pairs spins 0, 2 and 1, 3 with unit entries");
 __device__ __forceinline__ double2 xpy_m(const double2 X[4][4], const double2 Y[4][4], const double2 M[4][4],
                                         double hp) {
-    double2 z = make_double2(0.0, 0.0);
+    const double sg = hp > 0.0 ? 1.0 : -1.0;
+    // four independent partial sums (one per colour column c), so that the
+    // FP64 multiply-add chains stay short
+    double2 zc[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        // column g of X P: 1/2 X[r][g] + hp sum_{g'} X[r][g'] gamma_4[g'][g]
-        // (gamma_4[g'][g] nonzero for g = gperm[g'])
-        int gs = 0;
+    for (int c = 0; c < 4; ++c) zc[c] = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (kGamma4.perm[k] == g) gs = k;
+    for (int k = 0; k < 2; ++k) {
+        double2 xu[4];  // X u_k
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double2 ym = make_double2(0.0, 0.0);  // (Y M^T)_{g r}
+        for (int r = 0; r < 4; ++r)
+            xu[r] = make_double2(fmadd(sg, X[r][k + 2].x, X[r][k].x), fmadd(sg, X[r][k + 2].y, X[r][k].y));
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cmac(ym, Y[g][c], M[r][c]);
-            const double2 xg = times_ik(X[r][gs], kGamma4.code[gs]);
-            const double2 xp = make_double2(0.5 * X[r][g].x + hp * xg.x, 0.5 * X[r][g].y + hp * xg.y);
-            cmac(z, xp, ym);
+        for (int c = 0; c < 4; ++c) {
+            double2 mx = make_double2(0.0, 0.0);  // (M^T X u_k)_c
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cmac(mx, M[r][c], xu[r]);
+            const double2 yu = make_double2(fmadd(sg, Y[k + 2][c].x, Y[k][c].x), fmadd(sg, Y[k + 2][c].y, Y[k][c].y));
+            cmac(zc[c], yu, mx);
         }
     }
-    return z;
+    const double2 z = make_double2((zc[0].x + zc[1].x) + (zc[2].x + zc[3].x), (zc[0].y + zc[1].y) + (zc[2].y + zc[3].y));
+    return make_double2(0.5 * z.x, 0.5 * z.y);
 }
 
 // WD (Tr[P Y] <X, M> + Tr[P X] <Y, M>) + WE (<X P Y, M> + <Y P X, M>): the
