@@ -674,8 +674,9 @@ __device__ __forceinline__ void load_block(const char* const* cols, int32_t s, d
             const Chunk<T> c = __builtin_bit_cast(Chunk<T>, f.load(e / CE, so16));
             const T v = c.v[e % CE];
             if constexpr (PREC == QDP_F16S) {
-                const float2 d = f16s_decode(v, scale);
-                X[r][rp] = make_double2(d.x, d.y);
+                // an FMA with a +0 addend converts and scales in one mixed-precision
+                // instruction (exact: the scale is a power of two)
+                X[r][rp] = make_double2(__builtin_fmaf((float)v.x, scale, 0.0f), __builtin_fmaf((float)v.y, scale, 0.0f));
             } else {
                 X[r][rp] = make_double2(v.x, v.y);
             }
@@ -779,7 +780,8 @@ struct BaryonKind {
     static constexpr int NMU = KIND == QDP_BARYON_PROTON ? 1 : 3;
 };
 
-// M += G D G' with signed permutations:
+// M += G D G' with signed permutations (M = G D G' for the first mu, which
+// writes every element: G' permutes the columns):
 // M[r][G'.perm[q]] += i^(G.code[r] + G'.code[q]) D[G.perm[r]][q]
 template <int KIND, int MU>
 __device__ __forceinline__ void add_diquark(const double2 D[4][4], double2 M[4][4]) {
@@ -789,8 +791,12 @@ __device__ __forceinline__ void add_diquark(const double2 D[4][4], double2 M[4][
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double2 z = times_ik(D[K::G.perm[r]][q], K::G.code[r] + K::Gp.code[q]);
-            M[r][K::Gp.perm[q]].x += z.x;
-            M[r][K::Gp.perm[q]].y += z.y;
+            if constexpr (MU == 0) {
+                M[r][K::Gp.perm[q]] = z;
+            } else {
+                M[r][K::Gp.perm[q]].x += z.x;
+                M[r][K::Gp.perm[q]].y += z.y;
+            }
         }
 }
 
@@ -806,10 +812,6 @@ __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, d
     {
         double2 D[4][4];
         load_block<PREC, BUF, B, BP>(A.sd, s, D);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) M[r][q] = make_double2(0.0, 0.0);
         add_diquark<KIND, 0>(D, M);
         if constexpr (K::NMU > 1) add_diquark<KIND, 1>(D, M);
         if constexpr (K::NMU > 2) add_diquark<KIND, 2>(D, M);
