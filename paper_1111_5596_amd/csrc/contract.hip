@@ -684,6 +684,65 @@ __device__ __forceinline__ void load_block(const char* const* cols, int32_t s, d
     }
 }
 
+// F16S propagator of a wavefront's 64 sites staged in LDS: one 256-byte row
+// (64 lanes x one half2) per component e of column j (row 12 j + e), then one
+// row of FP32 record scales per column (row 144 + j).  The rows are filled by
+// the buffer-to-LDS copy path (4 bytes per lane, no registers), so that the
+// nine colour steps read the blocks they use from LDS: a site's 12 columns
+// are fetched once instead of once per block that uses them (each u block
+// enters four colour steps).
+constexpr int kBaryonLdsRows = 12 * 12 + 12;
+constexpr int kBaryonLdsWaveBytes = kBaryonLdsRows * 256;
+
+typedef __attribute__((address_space(3))) void baryon_lds_void_t;
+
+// Copies the 12 columns at site s (this lane's) into the wavefront's rows at
+// `rows`; the copies are complete after the wait below.
+__device__ __forceinline__ void stage_propagator_f16s(const char* const* cols, int32_t s, char* rows) {
+    const int64_t tb = tile_bytes(1, 12, QDP_F16S);
+    const int32_t vo16 = (int32_t)tile_site_offset(tb, 16, s), vo4 = (int32_t)site_off<float>(s, tb);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(cols[j]);
+#pragma unroll
+        for (int e = 0; e < 12; ++e)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (baryon_lds_void_t*)(rows + (12 * j + e) * 256), 4, vo16,
+                                                     (e / 4) * 1024 + (e % 4) * 4, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (baryon_lds_void_t*)(rows + (144 + j) * 256), 4, vo4, 12 * 256,
+                                                 0, 0);
+    }
+}
+
+// Waits until this wavefront's copies into LDS have landed; the memory
+// clobber keeps the compiler from moving LDS reads above the wait.
+__device__ __forceinline__ void wait_staged() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// load_block from the staged rows (`lane_rows` = the rows' base + 4 lane).
+template <int A, int AP>
+__device__ __forceinline__ void load_block_lds(const char* lane_rows, double2 X[4][4]) {
+#pragma unroll
+    for (int rp = 0; rp < 4; ++rp) {
+        const int j = 3 * rp + AP;
+        const float scale = *reinterpret_cast<const float*>(lane_rows + (144 + j) * 256);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const half2_t v = *reinterpret_cast<const half2_t*>(lane_rows + (12 * j + 3 * r + A) * 256);
+            X[r][rp] = make_double2(__builtin_fmaf((float)v.x, scale, 0.0f), __builtin_fmaf((float)v.y, scale, 0.0f));
+        }
+    }
+}
+
+// A block of u (D = false) or d (D = true): from the staged rows when LDS
+// holds that propagator (SRC = 1: u; SRC = 2: u, which is also d), else
+// from memory.
+template <int PREC, bool BUF, int SRC, bool D, int A, int AP>
+__device__ __forceinline__ void get_block(const BaryonArgs& a, int32_t s, const char* lane_rows, double2 X[4][4]) {
+    if constexpr (SRC == 2 || (SRC == 1 && !D))
+        load_block_lds<A, AP>(lane_rows, X);
+    else
+        load_block<PREC, BUF, A, AP>(D ? a.sd : a.su, s, X);
+}
+
 __device__ __forceinline__ double2 cmul(double2 u, double2 v) {
     double2 z = make_double2(0.0, 0.0);
     cmac(z, u, v);
@@ -801,8 +860,8 @@ __device__ __forceinline__ void add_diquark(const double2 D[4][4], double2 M[4][
 }
 
 // One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ].
-template <int PREC, bool BUF, int B, int BP, int KIND>
-__device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, double hp) {
+template <int PREC, bool BUF, int SRC, int B, int BP, int KIND>
+__device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, const char* lane_rows, double hp) {
     using K = BaryonKind<KIND, 0>;
     constexpr int X0 = B == 0 ? 1 : 0, Y0 = B == 2 ? 1 : 2;
     constexpr int XP = BP == 0 ? 1 : 0, YP = BP == 2 ? 1 : 2;
@@ -811,23 +870,23 @@ __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, d
     double2 M[4][4];
     {
         double2 D[4][4];
-        load_block<PREC, BUF, B, BP>(A.sd, s, D);
+        get_block<PREC, BUF, SRC, true, B, BP>(A, s, lane_rows, D);
         add_diquark<KIND, 0>(D, M);
         if constexpr (K::NMU > 1) add_diquark<KIND, 1>(D, M);
         if constexpr (K::NMU > 2) add_diquark<KIND, 2>(D, M);
     }
     double2 X[4][4], Y[4][4];
-    load_block<PREC, BUF, X0, XP>(A.su, s, X);
-    load_block<PREC, BUF, Y0, YP>(A.su, s, Y);
+    get_block<PREC, BUF, SRC, false, X0, XP>(A, s, lane_rows, X);
+    get_block<PREC, BUF, SRC, false, Y0, YP>(A, s, lane_rows, Y);
     const double2 f1 = pair_term<K::WD, K::WE>(X, Y, M, hp);
-    load_block<PREC, BUF, X0, YP>(A.su, s, X);
-    load_block<PREC, BUF, Y0, XP>(A.su, s, Y);
+    get_block<PREC, BUF, SRC, false, X0, YP>(A, s, lane_rows, X);
+    get_block<PREC, BUF, SRC, false, Y0, XP>(A, s, lane_rows, Y);
     const double2 f2 = pair_term<K::WD, K::WE>(X, Y, M, hp);
     return make_double2(SG * (f1.x - f2.x), SG * (f1.y - f2.y));
 }
 
-template <int PREC, bool BUF, int KIND>
-__device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, double hp) {
+template <int PREC, bool BUF, int SRC, int KIND>
+__device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, const char* lane_rows, double hp) {
     double2 acc = make_double2(0.0, 0.0);
     // the nine colour steps run one after another (a runtime loop, so the
     // compiler keeps one step's blocks live at a time)
@@ -835,15 +894,15 @@ __device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, do
     for (int bb = 0; bb < 9; ++bb) {
         double2 d;
         switch (__builtin_amdgcn_readfirstlane(bb)) {
-            case 0: d = colour_step<PREC, BUF, 0, 0, KIND>(A, s, hp); break;
-            case 1: d = colour_step<PREC, BUF, 0, 1, KIND>(A, s, hp); break;
-            case 2: d = colour_step<PREC, BUF, 0, 2, KIND>(A, s, hp); break;
-            case 3: d = colour_step<PREC, BUF, 1, 0, KIND>(A, s, hp); break;
-            case 4: d = colour_step<PREC, BUF, 1, 1, KIND>(A, s, hp); break;
-            case 5: d = colour_step<PREC, BUF, 1, 2, KIND>(A, s, hp); break;
-            case 6: d = colour_step<PREC, BUF, 2, 0, KIND>(A, s, hp); break;
-            case 7: d = colour_step<PREC, BUF, 2, 1, KIND>(A, s, hp); break;
-            default: d = colour_step<PREC, BUF, 2, 2, KIND>(A, s, hp); break;
+            case 0: d = colour_step<PREC, BUF, SRC, 0, 0, KIND>(A, s, lane_rows, hp); break;
+            case 1: d = colour_step<PREC, BUF, SRC, 0, 1, KIND>(A, s, lane_rows, hp); break;
+            case 2: d = colour_step<PREC, BUF, SRC, 0, 2, KIND>(A, s, lane_rows, hp); break;
+            case 3: d = colour_step<PREC, BUF, SRC, 1, 0, KIND>(A, s, lane_rows, hp); break;
+            case 4: d = colour_step<PREC, BUF, SRC, 1, 1, KIND>(A, s, lane_rows, hp); break;
+            case 5: d = colour_step<PREC, BUF, SRC, 1, 2, KIND>(A, s, lane_rows, hp); break;
+            case 6: d = colour_step<PREC, BUF, SRC, 2, 0, KIND>(A, s, lane_rows, hp); break;
+            case 7: d = colour_step<PREC, BUF, SRC, 2, 1, KIND>(A, s, lane_rows, hp); break;
+            default: d = colour_step<PREC, BUF, SRC, 2, 2, KIND>(A, s, lane_rows, hp); break;
         }
         acc.x += d.x;
         acc.y += d.y;
@@ -862,7 +921,7 @@ __global__ __launch_bounds__(256) void baryon_kernel(BaryonArgs A) {
     for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
         const int64_t p = l >= Vsh ? 1 : 0;
         const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
-        const double2 d = colour_sum<PREC, BUF, KIND>(A, s, hp);
+        const double2 d = colour_sum<PREC, BUF, 0, KIND>(A, s, nullptr, hp);
         acc.x += d.x;
         acc.y += d.y;
     }
@@ -878,6 +937,48 @@ __global__ __launch_bounds__(256) void baryon_kernel(BaryonArgs A) {
         double* out = A.partial + ((int64_t)t * A.nchunks + chunk) * 2;
         out[0] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
         out[1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    }
+}
+
+// F16S, buffer addressing: the same sums with each wavefront's u propagator
+// (and d, when SAME: d = u) staged in LDS per site.  One block of four
+// wavefronts per compute unit (the staging rows take 156 KiB of LDS), which
+// is the occupancy the register use allows anyway.
+template <int KIND, bool SAME>
+__global__ __launch_bounds__(256) void baryon_lds_kernel(BaryonArgs A) {
+    __shared__ __attribute__((aligned(16))) char rows[4 * kBaryonLdsWaveBytes];
+    const int t = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int64_t Vsh = A.g.Vsh;
+    const int64_t Vs = 2 * Vsh;
+    const double hp = 0.5 * A.parity;
+    const int w = threadIdx.x >> 6;
+    char* wrows = rows + __builtin_amdgcn_readfirstlane(w) * kBaryonLdsWaveBytes;
+    const char* lane_rows = wrows + 4 * (threadIdx.x & 63);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
+        const int64_t p = l >= Vsh ? 1 : 0;
+        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
+        // every LDS read of the previous site has returned (its values were
+        // summed into acc), so the rows can be overwritten
+        stage_propagator_f16s(A.su, s, wrows);
+        wait_staged();
+        const double2 d = colour_sum<QDP_F16S, true, SAME ? 2 : 1, KIND>(A, s, lane_rows, hp);
+        acc.x += d.x;
+        acc.y += d.y;
+    }
+    __syncthreads();  // the staging rows are reused for the block's partial sums
+    double* red = reinterpret_cast<double*>(rows);
+    const double re = wave_sum(acc.x), im = wave_sum(acc.y);
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * w] = re;
+        red[2 * w + 1] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* out = A.partial + ((int64_t)t * A.nchunks + chunk) * 2;
+        out[0] = (red[0] + red[2]) + (red[4] + red[6]);
+        out[1] = (red[1] + red[3]) + (red[5] + red[7]);
     }
 }
 
@@ -1136,7 +1237,15 @@ void* baryon_func_kind(int prec) {
         default: return reinterpret_cast<void*>(&baryon_kernel<QDP_F16S, BUF, KIND>);
     }
 }
-void* baryon_func(int prec, bool buf, int kind) {
+// F16S with buffer addressing stages the propagator in LDS (both
+// propagators when the u and d columns are the same fields).
+void* baryon_func(int prec, bool buf, int kind, bool same) {
+    if (prec == QDP_F16S && buf) {
+        if (kind == QDP_BARYON_PROTON)
+            return same ? reinterpret_cast<void*>(&baryon_lds_kernel<QDP_BARYON_PROTON, true>)
+                        : reinterpret_cast<void*>(&baryon_lds_kernel<QDP_BARYON_PROTON, false>);
+        return reinterpret_cast<void*>(&baryon_lds_kernel<QDP_BARYON_DELTA_PP, true>);
+    }
     if (kind == QDP_BARYON_PROTON) return buf ? baryon_func_kind<true, QDP_BARYON_PROTON>(prec)
                                               : baryon_func_kind<false, QDP_BARYON_PROTON>(prec);
     return buf ? baryon_func_kind<true, QDP_BARYON_DELTA_PP>(prec) : baryon_func_kind<false, QDP_BARYON_DELTA_PP>(prec);
@@ -1190,8 +1299,10 @@ qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd
     double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
     void* args[] = {&a};
     const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
-    QDP_HIP(ctx, hipLaunchKernel(baryon_func(prec, buf, kind), dim3((unsigned)nchunks, (unsigned)Lt), dim3(256),
-                                 args, 0, ctx->stream));
+    bool same = true;
+    for (int c = 0; c < 12; ++c) same = same && a.su[c] == a.sd[c];
+    QDP_HIP(ctx, hipLaunchKernel(baryon_func(prec, buf, kind, same), dim3((unsigned)nchunks, (unsigned)Lt),
+                                 dim3(256), args, 0, ctx->stream));
     QDP_CHECK(check_launch(ctx, "baryon kernel"));
     hipLaunchKernelGGL(baryon_finish, dim3((Lt + 255) / 256), dim3(256), 0, ctx->stream, a.partial, Lt,
                        (int32_t)nchunks, t0, d_out);
