@@ -115,8 +115,12 @@ enum qdp_smear_mode {
 
 /* Flags for qdp_init_opts.flags. */
 enum {
-    QDP_INIT_NO_AUTOTUNE = 1u << 0, /* use the default launch shapes */
-    QDP_INIT_NO_GRAPH = 1u << 1     /* launch smearing iterations one by one */
+    QDP_INIT_NO_AUTOTUNE = 1u << 0,    /* use the default launch shapes */
+    QDP_INIT_NO_GRAPH = 1u << 1,       /* launch smearing iterations one by one */
+    QDP_INIT_FLAT_ADDRESSING = 1u << 2 /* 64-bit flat addresses in every kernel
+                                          (the form fields of 4 GiB or more
+                                          take; buffer addressing otherwise),
+                                          so that form can be run at any size */
 };
 
 typedef struct {

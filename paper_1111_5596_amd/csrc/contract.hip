@@ -1121,7 +1121,7 @@ qdp_status meson_launch(Ctx* ctx, ContractArgs& a, int32_t prec, bool mom, uint3
     const int32_t Lt = a.g.L[3];
     const int32_t nq = mom ? kMomPerLaunch : 1;
     void* args[] = {&a};
-    const bool buf = field_bytes(a.g, QDP_FERMION, prec) < (int64_t(1) << 32);
+    const bool buf = field_bytes(a.g, QDP_FERMION, prec) < (int64_t(1) << 32) && !(ctx->flags & QDP_INIT_FLAT_ADDRESSING);
     bool alias = true;
     for (int c = 0; c < 12; ++c) alias = alias && a.s1[c] == a.s2[c];
     if (meson_by_colour(prec, mom, alias)) {
@@ -1298,7 +1298,7 @@ qdp_status baryon_contract_impl(Ctx* ctx, const uint64_t* Su, const uint64_t* Sd
     a.partial = reinterpret_cast<double*>(scratch.ptr());
     double* d_out = reinterpret_cast<double*>(scratch.ptr() + ((partial_bytes + 255) & ~size_t(255)));
     void* args[] = {&a};
-    const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32);
+    const bool buf = field_bytes(g, QDP_FERMION, prec) < (int64_t(1) << 32) && !(ctx->flags & QDP_INIT_FLAT_ADDRESSING);
     bool same = true;
     for (int c = 0; c < 12; ++c) same = same && a.su[c] == a.sd[c];
     QDP_HIP(ctx, hipLaunchKernel(baryon_func(prec, buf, kind, same), dim3((unsigned)nchunks, (unsigned)Lt),

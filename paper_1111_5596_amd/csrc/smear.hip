@@ -932,8 +932,9 @@ qdp_status check_aliasing(Ctx* ctx, const uint64_t* src, const uint64_t* dst, in
 }
 
 // Buffer addressing needs every byte offset of the links and of a column
-// below 4 GiB.
+// below 4 GiB (and is off in a context made with QDP_INIT_FLAT_ADDRESSING).
 bool needs_flat(Ctx* ctx, uint64_t gauge, uint64_t lattice, int32_t prec) {
+    if (ctx->flags & QDP_INIT_FLAT_ADDRESSING) return true;
     const Geometry& g = find_lattice(ctx, lattice)->geo;
     const int64_t limit = (int64_t(1) << 32) - 1;
     return find_field(ctx, gauge)->bytes > limit || field_bytes(g, QDP_FERMION, prec) > limit;

@@ -29,7 +29,7 @@ SUBSETS = {"all": 0, "even": 1, "odd": 2, "timeslice": 3}
 SETS = {"all": 0, "parity": 1, "timeslice": 2}
 ASSIGN = {"=": 0, "+=": 1, "-=": 2, "*=": 3}
 SMEAR_FULL, SMEAR_EVEN_ODD = 0, 1
-INIT_NO_AUTOTUNE, INIT_NO_GRAPH = 1, 2
+INIT_NO_AUTOTUNE, INIT_NO_GRAPH, INIT_FLAT_ADDRESSING = 1, 2, 4
 RANDOM_SU3, RANDOM_GAUSSIAN = 0, 1
 BARYON_PROTON, BARYON_DELTA_PP = 0, 1
 OPS = {"field": 0, "gauge": 1, "real_const": 2, "complex_const": 3, "shift": 4, "neg": 5,

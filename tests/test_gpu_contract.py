@@ -246,6 +246,37 @@ def test_delta_pp_two_point(qdp, prec, dims):
         qdp.free(f)
 
 
+def test_flat_addressing_matches_buffer_bitwise(qdp):
+    """A context made with INIT_FLAT_ADDRESSING runs the contraction kernels'
+    64-bit flat-address form (the one fields of 4 GiB or more take) at a small
+    size: mesons at zero and four momenta, with and without aliased columns,
+    the proton (u != d and u = d) and the Delta++ give the bits of the
+    buffer-addressed form (for F16S baryons: the LDS-staged kernel against the
+    one reading every block from memory)."""
+    from paper_1111_5596_amd import qdpmi
+
+    dims = (6, 4, 4, 6)
+    Su = synth.gaussian_propagator(dims, 211)
+    Sd = synth.gaussian_propagator(dims, 212)
+    moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    flat = qdpmi.Context(pool_bytes=1 << 30, flags=qdpmi.INIT_FLAT_ADDRESSING)
+    try:
+        for prec in ("F64", "F32", "F16S"):
+            res = []
+            for q in (qdp, flat):
+                lat = q.lattice(dims)
+                u = upload_cols(q, lat, Su, prec)
+                d = upload_cols(q, lat, Sd, prec)
+                res.append([q.contract(u, d), q.contract(u, u), q.contract_mom(u, d, moms),
+                            q.contract_mom(u, u, moms), q.nucleon(u, d), q.nucleon(u, u), q.delta(u)])
+                for f in u + d:
+                    q.free(f)
+            for k, (a, b) in enumerate(zip(*res)):
+                assert np.array_equal(a, b), (prec, k)
+    finally:
+        flat.close()
+
+
 @pytest.mark.parametrize("prec", ["F32", "F16S"])
 def test_aliased_columns_match_copies_bitwise(qdp, prec):
     """S1 and S2 naming the same columns (read once per site) gives the same
