@@ -1000,10 +1000,11 @@ qdp_status choose_shape(Ctx* ctx, const SmearTuneKey& key, int prec, const Smear
                             cands.push_back(qdp_launch_shape{sw, cg, xcd, occ, flat, zs, 0});
                         }
             }
-        // the banded orders first: they fetch fewer bytes, so on a tie
-        // within the timing margin the one that loads the memory system
-        // less is kept
-        for (int S : {1, 2})
+        // two-wave rows (S = 2) and the banded orders first: they fetch
+        // fewer bytes, so on a tie within the timing margin the one that
+        // loads the memory system less is kept (over whole smearing runs it
+        // is also the faster one)
+        for (int S : {2, 1})
             for (int xcd : {0, 1})
                 for (int zs : {1, 2, 0}) {
                     const qdp_launch_shape sh{1, 1, xcd, 0, flat, zs, S};
