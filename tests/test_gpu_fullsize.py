@@ -228,20 +228,25 @@ def test_batch_of_64_uneven_lattices(qdp):
 def test_48cubed_96_hadron_contractions_sampled(qdp):
     """The benchmark's other contractions at full size, in its configuration:
     the 48^3 x 96 F16S Gaussian propagator (device generator, seed 105),
-    mesons at four momenta, the proton (both parities, u = d) and the Delta++,
-    checked on time slice 29 against the oracle run on that slice's stored
-    values (the plane wave uses the spatial coordinates only, so a slice is an
-    independent oracle problem)."""
+    mesons at four momenta, the proton (both parities with u = d, and with a
+    second propagator, seed 106, as d) and the Delta++, checked on time slice
+    29 against the oracle run on that slice's stored values (the plane wave
+    uses the spatial coordinates only, so a slice is an independent oracle
+    problem).  Each lane of the baryon launch takes several sites here, so the
+    per-site staging of the propagator in LDS is exercised repeatedly."""
     dims = (48, 48, 48, 96)
     V = synth.volume(dims)
     sd = (48, 48, 48, 1)
     t = 29
     lat = qdp.lattice(dims)
     cols = [qdp.alloc(lat, "FERMION", "F16S") for _ in range(12)]
+    cols2 = [qdp.alloc(lat, "FERMION", "F16S") for _ in range(12)]
     try:
-        for j, f in enumerate(cols):
-            qdp.fill_gaussian(f, 105, j, (24.0 * V) ** -0.5)
+        for j in range(12):
+            qdp.fill_gaussian(cols[j], 105, j, (24.0 * V) ** -0.5)
+            qdp.fill_gaussian(cols2[j], 106, j, (24.0 * V) ** -0.5)
         S = np.stack([qdp.read_timeslices(f, t, t + 1) for f in cols])
+        S2 = np.stack([qdp.read_timeslices(f, t, t + 1) for f in cols2])
         moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
         got = qdp.contract_mom(cols, cols, moms)[:, :, t]
         ref = oracle.meson_mom(S, S, sd, moms)[:, :, 0]
@@ -251,9 +256,12 @@ def test_48cubed_96_hadron_contractions_sampled(qdp):
             got = qdp.nucleon(cols, cols, parity=parity)[t]
             ref = oracle.nucleon(S, S, sd, parity)[0]
             assert abs(got - ref) <= 1e-10 * abs(ref), parity
+        got = qdp.nucleon(cols, cols2)[t]
+        ref = oracle.nucleon(S, S2, sd, 1)[0]
+        assert abs(got - ref) <= 1e-10 * abs(ref)
         got = qdp.delta(cols)[t]
         ref = oracle.delta(S, sd, 1)[0]
         assert abs(got - ref) <= 1e-10 * abs(ref)
     finally:
-        for f in cols:
+        for f in cols + cols2:
             qdp.free(f)
