@@ -208,18 +208,35 @@ __device__ __forceinline__ double2 times_ik(double2 z, int k) {
     }
 }
 
+// Spatial coordinates of index l within the sites of time slice t (l = p Vsh
+// + x/2 + (Lx/2)(y + Ly z) for the site of parity p; the parity fixes the low
+// bit of x).  32-bit arithmetic: a time slice holds fewer than 2^31 sites.
+__device__ __forceinline__ void slice_coords(const Geometry& g, uint32_t l, int32_t t, int32_t c[3]) {
+    const uint32_t Vsh = (uint32_t)g.Vsh, Lxh = (uint32_t)g.Lxh, Ly = (uint32_t)g.L[1];
+    const uint32_t p = l >= Vsh ? 1u : 0u;
+    const uint32_t i = l - p * Vsh;
+    const uint32_t yz = i / Lxh, z = yz / Ly;
+    const uint32_t y = yz - z * Ly, xh = i - yz * Lxh;
+    c[0] = (int32_t)(2 * xh + ((p + y + z + (uint32_t)t) & 1u));
+    c[1] = (int32_t)y;
+    c[2] = (int32_t)z;
+}
+
 // exp(-i p.x) for integer momentum k at spatial coordinates c: the phase
-// angle is reduced exactly to a fraction num / (Lx Ly Lz) of a turn first.
-__device__ __forceinline__ double2 plane_wave(const Geometry& g, const int32_t k[3], const int32_t c[4]) {
-    const int64_t M = (int64_t)g.L[0] * g.L[1] * g.L[2];
-    int64_t num = 0;
+// angle is reduced exactly to a fraction num / (Lx Ly Lz) of a turn first
+// (each k_i c_i mod L_i, k_i reduced mod L_i first, so every product and
+// partial sum fits 32 bits: L_i^2 < 2^31 and the sum stays below 2 Lx Ly Lz).
+__device__ __forceinline__ double2 plane_wave(const Geometry& g, const int32_t k[3], const int32_t c[3]) {
+    const uint32_t M = (uint32_t)g.L[0] * (uint32_t)g.L[1] * (uint32_t)g.L[2];
+    uint32_t num = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        int64_t r = ((int64_t)k[i] * c[i]) % g.L[i];
-        if (r < 0) r += g.L[i];
-        num += r * (M / g.L[i]);
+        const int32_t L = g.L[i];
+        const uint32_t kr = (uint32_t)(((k[i] % L) + L) % L);
+        const uint32_t r = (kr * (uint32_t)c[i]) % (uint32_t)L;
+        num += r * (M / (uint32_t)L);
+        if (num >= M) num -= M;
     }
-    num %= M;
     double sn, cs;
     sincospi(-2.0 * ((double)num / (double)M), &sn, &cs);
     return make_double2(cs, sn);
@@ -316,8 +333,8 @@ __device__ __forceinline__ void meson_sites(const ContractArgs& A, int t, int ch
             source_spin(std::integral_constant<int, 3>{});
         }
         if constexpr (NMOM > 0) {
-            int32_t c[4];
-            cb_coords(A.g, s, c);
+            int32_t c[3];
+            slice_coords(A.g, (uint32_t)l, t, c);
 #pragma unroll
             for (int q = 0; q < NMOM; ++q) {
                 const double2 w = plane_wave(A.g, A.mom[q], c);
@@ -573,8 +590,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
             for (int e = 0; e < 16; ++e) hs[w][e][lane] = active ? H[e >> 2][e & 3] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        int32_t c[4];
-        cb_coords(A.g, s, c);
+        int32_t c[3];
+        slice_coords(A.g, (uint32_t)lc, t, c);
         const double2 ph = plane_wave(A.g, A.mom[w], c);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -1234,7 +1251,10 @@ void* baryon_func_kind(int prec) {
     switch (prec) {
         case QDP_F64: return reinterpret_cast<void*>(&baryon_kernel<QDP_F64, BUF, KIND>);
         case QDP_F32: return reinterpret_cast<void*>(&baryon_kernel<QDP_F32, BUF, KIND>);
-        default: return reinterpret_cast<void*>(&baryon_kernel<QDP_F16S, BUF, KIND>);
+        default:
+            // F16S with buffer addressing runs baryon_lds_kernel
+            if constexpr (BUF) return nullptr;
+            else return reinterpret_cast<void*>(&baryon_kernel<QDP_F16S, false, KIND>);
     }
 }
 // F16S with buffer addressing stages the propagator in LDS (both
