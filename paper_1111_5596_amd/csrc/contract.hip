@@ -553,10 +553,11 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void m
 }
 
 // Momentum-projected F16S contraction, four momenta per launch.  Waves 0..2
-// form a site's 16 sums H_sigma[k] for their source colour as above; the
-// three colours' sums meet in LDS, and wavefront q (0..3) adds them (fixed
-// order) and weights them by the plane wave of momentum q at the site, so
-// each site's phase is computed once per momentum.  C_n = sum_k f_n(k)
+// form a site's 16 sums H_sigma[k] for their source colour as above while
+// wave 3 forms the site's four plane waves; the three colours' sums and the
+// phases meet in LDS, and wavefront q (0..3) adds the sums (fixed order) and
+// weights them by the plane wave of momentum q at the site, so each site's
+// phase is computed once per momentum.  C_n = sum_k f_n(k)
 // H_sigma(n)[k] once per block, as at zero momentum.
 constexpr int kColourMomenta = 4;
 template <bool BUF, bool ALIAS>
@@ -566,6 +567,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // colour (w < 3) and momentum
     const int lane = threadIdx.x & 63;
     __shared__ double2 hs[3][16][64];
+    __shared__ double2 phs[kColourMomenta][64];
     double2 C[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) C[e] = make_double2(0.0, 0.0);
@@ -588,11 +590,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
             colour_site_sums<BUF, ALIAS>(A, s, w, H);
 #pragma unroll
             for (int e = 0; e < 16; ++e) hs[w][e][lane] = active ? H[e >> 2][e & 3] : make_double2(0.0, 0.0);
+        } else {
+            // meanwhile the fourth wavefront forms the sites' four plane waves
+            int32_t c[3];
+            slice_coords(A.g, (uint32_t)lc, t, c);
+#pragma unroll
+            for (int q = 0; q < kColourMomenta; ++q) phs[q][lane] = plane_wave(A.g, A.mom[q], c);
         }
         __syncthreads();
-        int32_t c[3];
-        slice_coords(A.g, (uint32_t)lc, t, c);
-        const double2 ph = plane_wave(A.g, A.mom[w], c);
+        const double2 ph = phs[w][lane];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const double2 a = hs[0][e][lane], b = hs[1][e][lane], d = hs[2][e][lane];
