@@ -246,6 +246,45 @@ def test_delta_pp_two_point(qdp, prec, dims):
         qdp.free(f)
 
 
+def test_decaying_propagator_keeps_per_slice_precision(qdp):
+    """Correlators fall off by orders of magnitude in time; every time slice
+    keeps its own relative precision.  F16S propagators whose magnitude drops
+    by 10^-4 per time slice (10^-28 over the 8 slices, beyond the range of
+    one FP16 scale; the record scales carry it), the oracle run on the stored
+    values: mesons (zero and four momenta) within the colour-sum tolerance of
+    each slice's zero-momentum C_15, the proton and the Delta++ within 1e-10 of each slice's
+    own value (their terms fall by 10^-12 per slice)."""
+    dims = (4, 4, 4, 8)
+    V = synth.volume(dims)
+    t = np.arange(V) // (4 * 4 * 4)  # lexicographic sites, t slowest
+    fac = (10.0 ** (-4.0 * t))[None, :, None, None]
+    lat = qdp.lattice(dims)
+    u = upload_cols(qdp, lat, synth.gaussian_propagator(dims, 241) * fac, "F16S")
+    d = upload_cols(qdp, lat, synth.gaussian_propagator(dims, 242) * fac, "F16S")
+    Sur = np.stack([qdp.read(f) for f in u])
+    Sdr = np.stack([qdp.read(f) for f in d])
+    moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    try:
+        ref = oracle.meson(Sur, Sdr, dims)
+        assert abs(ref[15, 7].real) < 1e-50 * abs(ref[15, 0].real)
+        assert corr_err(qdp.contract(u, d), ref) <= F16S_COLOUR_SUM_TOL
+        assert corr_err(qdp.contract(u, u), oracle.meson(Sur, Sur, dims)) <= F16S_COLOUR_SUM_TOL
+        refm = oracle.meson_mom(Sur, Sur, dims, moms)
+        gotm = qdp.contract_mom(u, u, moms)
+        # every |C_n(p, t)| is bounded by C_15(0, t) = sum_x |S(x)|^2 over the
+        # slice (at p != 0 the phases cancel, so C_15(p, t) bounds nothing)
+        c15 = np.abs(refm[0, 15].real)
+        for q in range(len(moms)):
+            assert np.max(np.abs(gotm[q] - refm[q]) / c15[None, :]) <= F16S_COLOUR_SUM_TOL, moms[q]
+        for got, ref in [(qdp.nucleon(u, d), oracle.nucleon(Sur, Sdr, dims, 1)),
+                         (qdp.nucleon(u, u), oracle.nucleon(Sur, Sur, dims, 1)),
+                         (qdp.delta(u), oracle.delta(Sur, dims, 1))]:
+            assert np.all(np.abs(got - ref) <= 1e-10 * np.abs(ref))
+    finally:
+        for f in u + d:
+            qdp.free(f)
+
+
 def test_flat_addressing_matches_buffer_bitwise(qdp):
     """A context made with INIT_FLAT_ADDRESSING runs the contraction kernels'
     64-bit flat-address form (the one fields of 4 GiB or more take) at a small
