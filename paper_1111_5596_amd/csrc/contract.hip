@@ -707,25 +707,27 @@ __device__ __forceinline__ void load_block(const char* const* cols, int32_t s, d
     }
 }
 
-// F16S propagator of a wavefront's 64 sites staged in LDS: one 256-byte row
-// (64 lanes x one half2) per component e of column j (row 12 j + e), then one
-// row of FP32 record scales per column (row 144 + j).  The rows are filled by
-// the buffer-to-LDS copy path (4 bytes per lane, no registers), so that the
-// nine colour steps read the blocks they use from LDS: a site's 12 columns
-// are fetched once instead of once per block that uses them (each u block
-// enters four colour steps).
+// F16S propagator of 64 sites staged in LDS: one 256-byte row (64 lanes x
+// one half2) per component e of column j (row 12 j + e), then one row of FP32
+// record scales per column (row 144 + j).  The rows are filled by the
+// buffer-to-LDS copy path (4 bytes per lane, no registers), so that the nine
+// colour steps read the blocks they use from LDS: a site's 12 columns are
+// fetched once instead of once per block that uses them (each u block enters
+// four colour steps).
 constexpr int kBaryonLdsRows = 12 * 12 + 12;
-constexpr int kBaryonLdsWaveBytes = kBaryonLdsRows * 256;
+constexpr int kBaryonLdsPairBytes = kBaryonLdsRows * 256;
 
 typedef __attribute__((address_space(3))) void baryon_lds_void_t;
 
-// Copies the 12 columns at site s (this lane's) into the wavefront's rows at
-// `rows`; the copies are complete after the wait below.
-__device__ __forceinline__ void stage_propagator_f16s(const char* const* cols, int32_t s, char* rows) {
+// Copies columns 6 half .. 6 half + 5 at site s (this lane's) into the rows
+// at `rows` (the two wavefronts sharing the rows copy one half each); the
+// copies are complete after the wait below.
+__device__ __forceinline__ void stage_propagator_half_f16s(const char* const* cols, int32_t s, char* rows, int half) {
     const int64_t tb = tile_bytes(1, 12, QDP_F16S);
     const int32_t vo16 = (int32_t)tile_site_offset(tb, 16, s), vo4 = (int32_t)site_off<float>(s, tb);
 #pragma unroll
-    for (int j = 0; j < 12; ++j) {
+    for (int jj = 0; jj < 6; ++jj) {
+        const int j = 6 * half + jj;
         const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(cols[j]);
 #pragma unroll
         for (int e = 0; e < 12; ++e)
@@ -882,8 +884,9 @@ __device__ __forceinline__ void add_diquark(const double2 D[4][4], double2 M[4][
         }
 }
 
-// One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ].
-template <int PREC, bool BUF, int SRC, int B, int BP, int KIND>
+// One (b, b') colour step of the sum: s_b s_b' [ f(U^{xx'}, U^{yy'}) - f(U^{xy'}, U^{yx'}) ]
+// (HALF = 1 or 2: only the first or only the second term, with its sign).
+template <int PREC, bool BUF, int SRC, int B, int BP, int KIND, int HALF = 0>
 __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, const char* lane_rows, double hp) {
     using K = BaryonKind<KIND, 0>;
     constexpr int X0 = B == 0 ? 1 : 0, Y0 = B == 2 ? 1 : 2;
@@ -899,16 +902,28 @@ __device__ __forceinline__ double2 colour_step(const BaryonArgs& A, int32_t s, c
         if constexpr (K::NMU > 2) add_diquark<KIND, 2>(D, M);
     }
     double2 X[4][4], Y[4][4];
-    get_block<PREC, BUF, SRC, false, X0, XP>(A, s, lane_rows, X);
-    get_block<PREC, BUF, SRC, false, Y0, YP>(A, s, lane_rows, Y);
-    const double2 f1 = pair_term<K::WD, K::WE>(X, Y, M, hp);
-    get_block<PREC, BUF, SRC, false, X0, YP>(A, s, lane_rows, X);
-    get_block<PREC, BUF, SRC, false, Y0, XP>(A, s, lane_rows, Y);
-    const double2 f2 = pair_term<K::WD, K::WE>(X, Y, M, hp);
-    return make_double2(SG * (f1.x - f2.x), SG * (f1.y - f2.y));
+    if constexpr (HALF == 1) {
+        get_block<PREC, BUF, SRC, false, X0, XP>(A, s, lane_rows, X);
+        get_block<PREC, BUF, SRC, false, Y0, YP>(A, s, lane_rows, Y);
+        const double2 f1 = pair_term<K::WD, K::WE>(X, Y, M, hp);
+        return make_double2(SG * f1.x, SG * f1.y);
+    } else if constexpr (HALF == 2) {
+        get_block<PREC, BUF, SRC, false, X0, YP>(A, s, lane_rows, X);
+        get_block<PREC, BUF, SRC, false, Y0, XP>(A, s, lane_rows, Y);
+        const double2 f2 = pair_term<K::WD, K::WE>(X, Y, M, hp);
+        return make_double2(-SG * f2.x, -SG * f2.y);
+    } else {
+        get_block<PREC, BUF, SRC, false, X0, XP>(A, s, lane_rows, X);
+        get_block<PREC, BUF, SRC, false, Y0, YP>(A, s, lane_rows, Y);
+        const double2 f1 = pair_term<K::WD, K::WE>(X, Y, M, hp);
+        get_block<PREC, BUF, SRC, false, X0, YP>(A, s, lane_rows, X);
+        get_block<PREC, BUF, SRC, false, Y0, XP>(A, s, lane_rows, Y);
+        const double2 f2 = pair_term<K::WD, K::WE>(X, Y, M, hp);
+        return make_double2(SG * (f1.x - f2.x), SG * (f1.y - f2.y));
+    }
 }
 
-template <int PREC, bool BUF, int SRC, int KIND>
+template <int PREC, bool BUF, int SRC, int KIND, int HALF = 0>
 __device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, const char* lane_rows, double hp) {
     double2 acc = make_double2(0.0, 0.0);
     // the nine colour steps run one after another (a runtime loop, so the
@@ -917,15 +932,15 @@ __device__ __forceinline__ double2 colour_sum(const BaryonArgs& A, int32_t s, co
     for (int bb = 0; bb < 9; ++bb) {
         double2 d;
         switch (__builtin_amdgcn_readfirstlane(bb)) {
-            case 0: d = colour_step<PREC, BUF, SRC, 0, 0, KIND>(A, s, lane_rows, hp); break;
-            case 1: d = colour_step<PREC, BUF, SRC, 0, 1, KIND>(A, s, lane_rows, hp); break;
-            case 2: d = colour_step<PREC, BUF, SRC, 0, 2, KIND>(A, s, lane_rows, hp); break;
-            case 3: d = colour_step<PREC, BUF, SRC, 1, 0, KIND>(A, s, lane_rows, hp); break;
-            case 4: d = colour_step<PREC, BUF, SRC, 1, 1, KIND>(A, s, lane_rows, hp); break;
-            case 5: d = colour_step<PREC, BUF, SRC, 1, 2, KIND>(A, s, lane_rows, hp); break;
-            case 6: d = colour_step<PREC, BUF, SRC, 2, 0, KIND>(A, s, lane_rows, hp); break;
-            case 7: d = colour_step<PREC, BUF, SRC, 2, 1, KIND>(A, s, lane_rows, hp); break;
-            default: d = colour_step<PREC, BUF, SRC, 2, 2, KIND>(A, s, lane_rows, hp); break;
+            case 0: d = colour_step<PREC, BUF, SRC, 0, 0, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 1: d = colour_step<PREC, BUF, SRC, 0, 1, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 2: d = colour_step<PREC, BUF, SRC, 0, 2, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 3: d = colour_step<PREC, BUF, SRC, 1, 0, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 4: d = colour_step<PREC, BUF, SRC, 1, 1, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 5: d = colour_step<PREC, BUF, SRC, 1, 2, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 6: d = colour_step<PREC, BUF, SRC, 2, 0, KIND, HALF>(A, s, lane_rows, hp); break;
+            case 7: d = colour_step<PREC, BUF, SRC, 2, 1, KIND, HALF>(A, s, lane_rows, hp); break;
+            default: d = colour_step<PREC, BUF, SRC, 2, 2, KIND, HALF>(A, s, lane_rows, hp); break;
         }
         acc.x += d.x;
         acc.y += d.y;
@@ -963,37 +978,48 @@ __global__ __launch_bounds__(256) void baryon_kernel(BaryonArgs A) {
     }
 }
 
-// F16S, buffer addressing: the same sums with each wavefront's u propagator
-// (and d, when SAME: d = u) staged in LDS per site.  One block of four
-// wavefronts per compute unit (the staging rows take 156 KiB of LDS), which
-// is the occupancy the register use allows anyway.
+// F16S, buffer addressing: the same sums with the u propagator (and d, when
+// SAME: d = u) staged in LDS per site, shared by a pair of wavefronts that
+// take the two pair terms of every colour step (HALF 1: f(U^{xx'}, U^{yy'}),
+// HALF 2: -f(U^{xy'}, U^{yx'})), so the 156 rows of 64 sites serve two
+// wavefronts: a block of two pairs takes 78 KiB of LDS and two blocks fit a
+// compute unit, two wavefronts per SIMD (rows per wavefront allowed one).
+// Each wavefront copies half of the columns; the block's barriers order the
+// copies and the reads.
 template <int KIND, bool SAME>
-__global__ __launch_bounds__(256) void baryon_lds_kernel(BaryonArgs A) {
-    __shared__ __attribute__((aligned(16))) char rows[4 * kBaryonLdsWaveBytes];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void baryon_pair_kernel(BaryonArgs A) {
+    __shared__ __attribute__((aligned(16))) char rows[2 * kBaryonLdsPairBytes];
     const int t = blockIdx.y;
     const int chunk = blockIdx.x;
     const int64_t Vsh = A.g.Vsh;
     const int64_t Vs = 2 * Vsh;
     const double hp = 0.5 * A.parity;
-    const int w = threadIdx.x >> 6;
-    char* wrows = rows + __builtin_amdgcn_readfirstlane(w) * kBaryonLdsWaveBytes;
-    const char* lane_rows = wrows + 4 * (threadIdx.x & 63);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pr = w >> 1, half = w & 1, lane = threadIdx.x & 63;
+    char* prows = rows + pr * kBaryonLdsPairBytes;
+    const char* lane_rows = prows + 4 * lane;
     double2 acc = make_double2(0.0, 0.0);
-    for (int64_t l = (int64_t)chunk * 256 + threadIdx.x; l < Vs; l += (int64_t)A.nchunks * 256) {
-        const int64_t p = l >= Vsh ? 1 : 0;
-        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (l - p * Vsh));
-        // every LDS read of the previous site has returned (its values were
-        // summed into acc), so the rows can be overwritten
-        stage_propagator_f16s(A.su, s, wrows);
+    for (int64_t base = (int64_t)chunk * 128; base < Vs; base += (int64_t)A.nchunks * 128) {
+        const int64_t l = base + 64 * pr + lane;
+        const bool active = l < Vs;
+        const int64_t lc = active ? l : Vs - 1;
+        const int64_t p = lc >= Vsh ? 1 : 0;
+        const int32_t s = (int32_t)(p * A.g.Vh + t * Vsh + (lc - p * Vsh));
+        __syncthreads();  // the previous sites' rows are no longer read
+        stage_propagator_half_f16s(A.su, s, prows, half);
         wait_staged();
-        const double2 d = colour_sum<QDP_F16S, true, SAME ? 2 : 1, KIND>(A, s, lane_rows, hp);
-        acc.x += d.x;
-        acc.y += d.y;
+        __syncthreads();  // both halves of the rows have landed
+        const double2 d = half ? colour_sum<QDP_F16S, true, SAME ? 2 : 1, KIND, 2>(A, s, lane_rows, hp)
+                               : colour_sum<QDP_F16S, true, SAME ? 2 : 1, KIND, 1>(A, s, lane_rows, hp);
+        if (active) {
+            acc.x += d.x;
+            acc.y += d.y;
+        }
     }
-    __syncthreads();  // the staging rows are reused for the block's partial sums
+    __syncthreads();
     double* red = reinterpret_cast<double*>(rows);
     const double re = wave_sum(acc.x), im = wave_sum(acc.y);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         red[2 * w] = re;
         red[2 * w + 1] = im;
     }
@@ -1258,19 +1284,19 @@ void* baryon_func_kind(int prec) {
         case QDP_F64: return reinterpret_cast<void*>(&baryon_kernel<QDP_F64, BUF, KIND>);
         case QDP_F32: return reinterpret_cast<void*>(&baryon_kernel<QDP_F32, BUF, KIND>);
         default:
-            // F16S with buffer addressing runs baryon_lds_kernel
+            // F16S with buffer addressing runs baryon_pair_kernel
             if constexpr (BUF) return nullptr;
             else return reinterpret_cast<void*>(&baryon_kernel<QDP_F16S, false, KIND>);
     }
 }
-// F16S with buffer addressing stages the propagator in LDS (both
-// propagators when the u and d columns are the same fields).
+// F16S with buffer addressing stages the propagator in LDS for wavefront
+// pairs (both propagators when the u and d columns are the same fields).
 void* baryon_func(int prec, bool buf, int kind, bool same) {
     if (prec == QDP_F16S && buf) {
         if (kind == QDP_BARYON_PROTON)
-            return same ? reinterpret_cast<void*>(&baryon_lds_kernel<QDP_BARYON_PROTON, true>)
-                        : reinterpret_cast<void*>(&baryon_lds_kernel<QDP_BARYON_PROTON, false>);
-        return reinterpret_cast<void*>(&baryon_lds_kernel<QDP_BARYON_DELTA_PP, true>);
+            return same ? reinterpret_cast<void*>(&baryon_pair_kernel<QDP_BARYON_PROTON, true>)
+                        : reinterpret_cast<void*>(&baryon_pair_kernel<QDP_BARYON_PROTON, false>);
+        return reinterpret_cast<void*>(&baryon_pair_kernel<QDP_BARYON_DELTA_PP, true>);
     }
     if (kind == QDP_BARYON_PROTON) return buf ? baryon_func_kind<true, QDP_BARYON_PROTON>(prec)
                                               : baryon_func_kind<false, QDP_BARYON_PROTON>(prec);

@@ -290,8 +290,10 @@ def test_flat_addressing_matches_buffer_bitwise(qdp):
     64-bit flat-address form (the one fields of 4 GiB or more take) at a small
     size: mesons at zero and four momenta, with and without aliased columns,
     the proton (u != d and u = d) and the Delta++ give the bits of the
-    buffer-addressed form (for F16S baryons: the LDS-staged kernel against the
-    one reading every block from memory)."""
+    buffer-addressed form; F16S baryons agree to FP64 rounding (there the
+    buffer form is the LDS-staged wavefront-pair kernel and the flat form
+    reads every block from memory: the same terms, summed in another
+    order)."""
     from paper_1111_5596_amd import qdpmi
 
     dims = (6, 4, 4, 6)
@@ -311,7 +313,13 @@ def test_flat_addressing_matches_buffer_bitwise(qdp):
                 for f in u + d:
                     q.free(f)
             for k, (a, b) in enumerate(zip(*res)):
-                assert np.array_equal(a, b), (prec, k)
+                if prec == "F16S" and k >= 4:
+                    # F16S baryons: the buffer form splits each colour step's two
+                    # terms over a pair of wavefronts, so its sums associate
+                    # differently (FP64 rounding only)
+                    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b)), (prec, k)
+                else:
+                    assert np.array_equal(a, b), (prec, k)
     finally:
         flat.close()
 
