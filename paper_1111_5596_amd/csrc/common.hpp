@@ -61,10 +61,11 @@ QDP_HD inline bool valid_prec(int32_t p) { return p >= QDP_F64 && p <= QDP_F16S;
 // the smearing brings the records of a site's neighbours to a common scale).
 constexpr float kF16sZeroScale = 0x1p-126f;
 
-// Bytes per complex component in a plane.
-QDP_HD inline int64_t prec_complex_bytes(int32_t prec) {
-    return prec == QDP_F64 ? 16 : (prec == QDP_F32 ? 8 : 4);
-}
+// Bytes per complex component in a plane (16, 8, 4: a power of two, so the
+// offsets below take shifts and masks, not divisions; kernels evaluate them
+// with the precision and record shape known only at run time).
+QDP_HD constexpr int32_t prec_log2_bytes(int32_t prec) { return prec == QDP_F64 ? 4 : (prec == QDP_F32 ? 3 : 2); }
+QDP_HD constexpr int64_t prec_complex_bytes(int32_t prec) { return int64_t(1) << prec_log2_bytes(prec); }
 
 struct Geometry {
     int32_t L[4];   // Lx, Ly, Lz, Lt
@@ -89,7 +90,7 @@ inline Geometry make_geometry(const int32_t d[4]) {
 }
 
 // Bytes of one 64-site tile of a field.
-QDP_HD inline int64_t tile_bytes(int32_t nrec, int32_t ncomp, int32_t prec) {
+QDP_HD constexpr int64_t tile_bytes(int32_t nrec, int32_t ncomp, int32_t prec) {
     return 64 * ((int64_t)nrec * ncomp * prec_complex_bytes(prec) + (prec == QDP_F16S ? 4 * (int64_t)nrec : 0));
 }
 
@@ -101,7 +102,7 @@ inline int64_t field_bytes(const Geometry& g, int32_t type, int32_t prec) {
 
 // Byte offset of row 0 of site `site` (elements of `esize` bytes) in a field
 // whose tiles are `tb` bytes.
-QDP_HD inline int64_t tile_site_offset(int64_t tb, int64_t esize, int64_t site) {
+QDP_HD constexpr int64_t tile_site_offset(int64_t tb, int64_t esize, int64_t site) {
     return (site >> 6) * tb + (site & 63) * esize;
 }
 
@@ -112,28 +113,52 @@ QDP_HD inline int64_t tile_site_offset(int64_t tb, int64_t esize, int64_t site) 
 // load covers 1024 contiguous bytes.  Fields whose per-site component count
 // is not a multiple of the chunk size (colour matrices, vectors and scalars
 // in F16S/F32) keep one row per component instead.
-QDP_HD inline int32_t chunk_elems(int32_t prec) { return (int32_t)(16 / prec_complex_bytes(prec)); }
-QDP_HD inline bool chunked_layout(int32_t nrec, int32_t ncomp, int32_t prec) {
-    return ((int64_t)nrec * ncomp) % chunk_elems(prec) == 0;
+QDP_HD constexpr int32_t chunk_elems(int32_t prec) { return 1 << (4 - prec_log2_bytes(prec)); }
+QDP_HD constexpr bool chunked_layout(int32_t nrec, int32_t ncomp, int32_t prec) {
+    return ((nrec * ncomp) & (chunk_elems(prec) - 1)) == 0;
 }
 
-// Byte offset of component k of record rec at `site`.
-QDP_HD inline int64_t comp_offset(int32_t nrec, int32_t ncomp, int32_t prec, int32_t rec, int32_t comp,
-                                  int64_t site) {
-    const int64_t es = prec_complex_bytes(prec);
+// Byte offset of component k of record rec at `site`: element e = rec ncomp
+// + k sits in chunk row e / CE at position e mod CE (chunked layout, CE =
+// chunk_elems), else in row e.
+QDP_HD constexpr int64_t comp_offset(int32_t nrec, int32_t ncomp, int32_t prec, int32_t rec, int32_t comp,
+                                     int64_t site) {
+    const int32_t les = prec_log2_bytes(prec), lce = 4 - les;
     const int64_t tb = tile_bytes(nrec, ncomp, prec);
-    const int64_t e = (int64_t)rec * ncomp + comp;
-    if (chunked_layout(nrec, ncomp, prec)) {
-        const int64_t ce = chunk_elems(prec);
-        return tile_site_offset(tb, 16, site) + (e / ce) * 64 * 16 + (e % ce) * es;
-    }
-    return tile_site_offset(tb, es, site) + e * 64 * es;
+    const int32_t e = rec * ncomp + comp;
+    if (chunked_layout(nrec, ncomp, prec))
+        return tile_site_offset(tb, 16, site) + ((int64_t)(e >> lce) << 10) + ((e & ((1 << lce) - 1)) << les);
+    return tile_site_offset(tb, int64_t(1) << les, site) + ((int64_t)e << (6 + les));
 }
 
 // Byte offset of the F16S scale of record rec at `site`.
-QDP_HD inline int64_t scale_offset(int32_t nrec, int32_t ncomp, int32_t rec, int64_t site) {
+QDP_HD constexpr int64_t scale_offset(int32_t nrec, int32_t ncomp, int32_t rec, int64_t site) {
     return tile_site_offset(tile_bytes(nrec, ncomp, QDP_F16S), 4, site) + ((int64_t)nrec * ncomp + rec) * 64 * 4;
 }
+
+// The shifts and masks above against the plain division form of the layout,
+// for every record shape, precision and component at sites in the first,
+// second and a later tile.
+constexpr bool layout_offsets_match_division_form() {
+    const int32_t shapes[][2] = {{1, 1}, {1, 3}, {1, 9}, {1, 12}, {1, 16}, {1, 144}, {4, 9}};
+    const int64_t sites[] = {0, 65, 1000};
+    for (const auto& sh : shapes)
+        for (int32_t prec = QDP_F64; prec <= QDP_F16S; ++prec) {
+            const int64_t es = prec == QDP_F64 ? 16 : (prec == QDP_F32 ? 8 : 4), ce = 16 / es;
+            const int64_t n = (int64_t)sh[0] * sh[1];
+            const int64_t tb = 64 * (n * es + (prec == QDP_F16S ? 4 * sh[0] : 0));
+            for (int32_t rec = 0; rec < sh[0]; ++rec)
+                for (int32_t k = 0; k < sh[1]; ++k)
+                    for (const int64_t site : sites) {
+                        const int64_t e = (int64_t)rec * sh[1] + k;
+                        const int64_t want = n % ce == 0 ? (site / 64) * tb + (site % 64) * 16 + (e / ce) * 1024 + (e % ce) * es
+                                                         : (site / 64) * tb + (site % 64) * es + e * 64 * es;
+                        if (comp_offset(sh[0], sh[1], prec, rec, k, site) != want) return false;
+                    }
+        }
+    return true;
+}
+static_assert(layout_offsets_match_division_form(), "tile layout offsets");
 
 // Checkerboard index of lexicographic coordinates.
 QDP_HD inline int64_t cb_index(const Geometry& g, int32_t x, int32_t y, int32_t z, int32_t t) {
@@ -141,16 +166,16 @@ QDP_HD inline int64_t cb_index(const Geometry& g, int32_t x, int32_t y, int32_t 
     return p * g.Vh + (x >> 1) + (int64_t)g.Lxh * (y + (int64_t)g.L[1] * (z + (int64_t)g.L[2] * t));
 }
 
+// 32-bit unsigned arithmetic: a lattice holds at most 2^31 sites.
 QDP_HD inline void cb_coords(const Geometry& g, int64_t s, int32_t c[4]) {
-    const int32_t p = s >= g.Vh ? 1 : 0;
-    int64_t i = s - p * g.Vh;
-    const int32_t h = (int32_t)(i % g.Lxh);
-    i /= g.Lxh;
-    c[1] = (int32_t)(i % g.L[1]);
-    i /= g.L[1];
-    c[2] = (int32_t)(i % g.L[2]);
-    c[3] = (int32_t)(i / g.L[2]);
-    c[0] = 2 * h + ((p + c[1] + c[2] + c[3]) & 1);
+    const uint32_t Vh = (uint32_t)g.Vh, Lxh = (uint32_t)g.Lxh, Ly = (uint32_t)g.L[1], Lz = (uint32_t)g.L[2];
+    const uint32_t p = (uint32_t)s >= Vh ? 1u : 0u;
+    const uint32_t i = (uint32_t)s - p * Vh;
+    const uint32_t r1 = i / Lxh, r2 = r1 / Ly, r3 = r2 / Lz;
+    c[1] = (int32_t)(r1 - r2 * Ly);
+    c[2] = (int32_t)(r2 - r3 * Lz);
+    c[3] = (int32_t)r3;
+    c[0] = (int32_t)(2 * (i - r1 * Lxh) + ((p + (uint32_t)c[1] + (uint32_t)c[2] + r3) & 1u));
 }
 
 }  // namespace qdpmi
