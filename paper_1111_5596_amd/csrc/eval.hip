@@ -183,14 +183,57 @@ __device__ __forceinline__ cplx_t<R> load_comp(const char* base, int32_t prec, i
     }
 }
 
+// N consecutive components of a chunked F32 or F16S field whose first one
+// sits at position OFF of its 16-byte chunk (p: that chunk at this site):
+// every chunk the run touches is loaded once, whole (the partly used first
+// and last chunks lie inside the site's record rows).
+template <typename R, typename E, int OFF, int N>
+__device__ __forceinline__ void load_run(const char* p, float sc, cplx_t<R>* v) {
+    constexpr int CE = 16 / (int)sizeof(E);
+    constexpr int NCH = (OFF + N + CE - 1) / CE;
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        const Chunk<E> w = __builtin_bit_cast(Chunk<E>, *reinterpret_cast<const u32x4_t*>(p + q * 1024));
+#pragma unroll
+        for (int j = 0; j < CE; ++j) {
+            const int k = q * CE + j - OFF;
+            if (k >= 0 && k < N) {
+                if constexpr (sizeof(E) == 4) v[k] = cplx_t<R>{(R)((float)w.v[j].x * sc), (R)((float)w.v[j].y * sc)};
+                else v[k] = cplx_t<R>{(R)w.v[j].x, (R)w.v[j].y};
+            }
+        }
+    }
+}
+
 // N consecutive components of record rec (from component 0): whole 16-byte
-// chunks when the record starts on a chunk boundary of a chunked field (F32:
-// 2 components per load, F16S: 4), else one component at a time.
+// chunks when the field is chunked (F32: 2 components per load, F16S: 4;
+// short runs such as a link of the gauge field from any position in its
+// chunk), else one component at a time.
 template <typename R, int N>
 __device__ __forceinline__ void load_comps(const char* base, int32_t prec, int32_t nrec, int32_t ncomp, int32_t rec,
                                            int32_t site, cplx_t<R>* v) {
     using T2 = cplx_t<R>;
     const int32_t e0 = rec * ncomp;
+    if constexpr (N <= 16) {
+        if (prec != QDP_F64 && chunked_layout(nrec, ncomp, prec)) {
+            // the chunk holding element e0
+            const int32_t les = prec_log2_bytes(prec), pos = e0 & ((1 << (4 - les)) - 1);
+            const char* p = base + comp_offset(nrec, ncomp, prec, rec, 0, site) - (pos << les);
+            if (prec == QDP_F32) {
+                if (pos == 0) load_run<R, float2, 0, N>(p, 1.f, v);
+                else load_run<R, float2, 1, N>(p, 1.f, v);
+            } else {
+                const float sc = *reinterpret_cast<const float*>(base + scale_offset(nrec, ncomp, rec, site));
+                switch (pos) {
+                    case 0: load_run<R, half2_t, 0, N>(p, sc, v); break;
+                    case 1: load_run<R, half2_t, 1, N>(p, sc, v); break;
+                    case 2: load_run<R, half2_t, 2, N>(p, sc, v); break;
+                    default: load_run<R, half2_t, 3, N>(p, sc, v); break;
+                }
+            }
+            return;
+        }
+    }
     if constexpr (N % 2 == 0) {
         if (prec == QDP_F32 && chunked_layout(nrec, ncomp, prec) && e0 % 2 == 0) {
             const char* p = base + comp_offset(nrec, ncomp, prec, rec, 0, site);
@@ -546,9 +589,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs A) {
         if (T.has_mat) {
             T2 m[9];
             const int32_t ms = T.mat.has_disp ? displaced_site(A.g, c, T.mat.d) : s;
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                m[k] = load_comp<R>(T.mat.base, T.mat.prec, T.mat.nrec, T.mat.ncomp, T.mat.rec, k, ms);
+            load_comps<R, 9>(T.mat.base, T.mat.prec, T.mat.nrec, T.mat.ncomp, T.mat.rec, ms, m);
 #pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp)
 #pragma unroll
