@@ -140,7 +140,7 @@ def test_launch_shapes_bitwise(qdp, prec):
 
 
 @pytest.mark.parametrize("dims", [(8, 8, 4, 4), (12, 12, 12, 4), (20, 20, 4, 2), (24, 12, 4, 2), (6, 6, 2, 2),
-                                  (48, 48, 8, 4), (16, 2, 4, 2), (16, 32, 4, 2)])
+                                  (48, 48, 8, 4), (16, 2, 4, 2), (16, 32, 4, 2), (64, 4, 4, 2), (68, 4, 2, 2)])
 @pytest.mark.parametrize("source", ["gaussian", "point"])
 def test_lds_window_kernel_bitwise(qdp, dims, source):
     """The whole-lattice F16S kernel that stages the x/y neighbour window in
@@ -152,8 +152,10 @@ def test_lds_window_kernel_bitwise(qdp, dims, source):
     against the kernels without LDS in both modes: windows that cover the
     whole parity range, a block range past the end of a parity (12^3 x 4:
     3456 indices per parity), y hops that wrap out of the window (20^2 and
-    48^2 planes) and Ly = 2; point sources (all-zero records beside non-zero
-    ones) and Gaussian columns."""
+    48^2 planes) and Ly = 2, the widest window (Lx = 64: the window is then
+    exactly the LDS rows, 64 (S + 1) indices) and a lattice too wide for it
+    (Lx = 68: the LDS shapes run the kernel without LDS); point sources
+    (all-zero records beside non-zero ones) and Gaussian columns."""
     U = synth.su3_links(dims, 17)
     if source == "point":
         psi = synth.point_source(dims, range(12), site=synth.volume(dims) // 3)
