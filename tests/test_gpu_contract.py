@@ -157,6 +157,11 @@ def test_meson_momentum_projection(qdp, prec, dims):
     # products); the plane wave carries about one ulp
     tol = F16S_COLOUR_SUM_TOL if prec == "F16S" else 1e-12
     assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+    # momenta that differ by whole multiples of the box (and near the int32
+    # limit) give the same phases: the angle is reduced exactly, so the bits
+    # are the same
+    shifted = [(k0 + 3 * dims[0], k1 - 5 * dims[1], k2 + (2 ** 30 // dims[2]) * dims[2]) for k0, k1, k2 in MOMS]
+    assert np.array_equal(qdp.contract_mom(a, b, shifted), got)
     # p = 0 agrees with the zero-momentum call
     c0 = qdp.contract(a, b)
     assert np.max(np.abs(got[0] - c0)) <= 1e-13 * np.max(np.abs(c0))
