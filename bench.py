@@ -44,6 +44,7 @@ KAPPA = 0.25
 NITER = 100
 LINK_SEED, PROP_SEED = 5, 105
 HBM_PEAK_GBPS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 FLOP_PER_SITE_UPDATE = 1752
 
 # Algorithmic HBM bytes per site-update used for the roofline (the
@@ -349,6 +350,23 @@ def run_hadron_extras(q, torch, lat):
             ts.append((time.perf_counter() - t0) * 1e3)
         out[name] = sorted(ts)[1]
     free_all(q, cols)
+    # rooflines on the wall times (launch, finish pass and the synchronising
+    # copy of the result included): the mesons read the 12 F16S columns once
+    # (52 B per site and column); the baryons are FP64 work, 2016 complex
+    # multiply-adds (8 flop each) per site: nine colour steps of two pair
+    # terms, each two 16-term inner products and two 40-term exchange traces
+    meson_bytes = 12 * 52 * V
+    baryon_flop = 2016 * 8 * V
+    rl = {}
+    for name in ("meson_p0_ms", "meson_4mom_ms"):
+        gbps = meson_bytes / (out[name] * 1e-3) / 1e9
+        rl[name[:-3]] = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": gbps / HBM_PEAK_GBPS, "bytes": meson_bytes}
+    for name in ("nucleon_ms", "delta_pp_ms"):
+        tf = baryon_flop / (out[name] * 1e-3) / 1e12
+        rl[name[:-3]] = {"bound": "fp64 vector", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "flop": baryon_flop}
+    out["roofline"] = rl
     return out
 
 
@@ -628,7 +646,7 @@ def main():
         res["c3"] = run_config3(q, torch)
         log(f"24^3x48: F16S {res['c3']['F16S']['ms']:.1f} ms, F32 {res['c3']['F32']['ms']:.1f} ms")
     hadron = run_hadron_extras(q, torch, lat)
-    log(f"hadron contractions {hadron}")
+    log(f"hadron contractions { {k: v for k, v in hadron.items() if k != 'roofline'} }")
     plain = None
     if not args.no_plain:
         plain = run_plain(q, torch, lat)
