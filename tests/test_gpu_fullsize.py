@@ -228,7 +228,8 @@ def test_batch_of_64_uneven_lattices(qdp):
 def test_48cubed_96_hadron_contractions_sampled(qdp):
     """The benchmark's other contractions at full size, in its configuration:
     the 48^3 x 96 F16S Gaussian propagator (device generator, seed 105),
-    mesons at four momenta, the proton (both parities with u = d, and with a
+    mesons at four momenta (and, with a second propagator, seed 106, at zero
+    and four momenta), the proton (both parities with u = d, and with a
     second propagator, seed 106, as d) and the Delta++, checked on time slice
     29 against the oracle run on that slice's stored values (the plane wave
     uses the spatial coordinates only, so a slice is an independent oracle
@@ -251,6 +252,13 @@ def test_48cubed_96_hadron_contractions_sampled(qdp):
         got = qdp.contract_mom(cols, cols, moms)[:, :, t]
         ref = oracle.meson_mom(S, S, sd, moms)[:, :, 0]
         # FP32 colour sums of exact products of the stored halves, FP64 after
+        assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+        # two distinct propagators: the other meson kernels, zero and four momenta
+        got = qdp.contract_mom(cols, cols2, moms)[:, :, t]
+        ref = oracle.meson_mom(S, S2, sd, moms)[:, :, 0]
+        assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+        got = qdp.contract(cols, cols2)[:, t]
+        ref = oracle.meson(S, S2, sd)[:, 0]
         assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
         for parity in (1, -1):
             got = qdp.nucleon(cols, cols, parity=parity)[t]
